@@ -1,0 +1,155 @@
+/*
+ * libtopk — unsorted top-k selection on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: the sampling selection of Hübschle-Schneider, Sanders, Müller,
+ * "Communication Efficient Algorithms for Top-k Selection Problems":
+ * §2 (Algorithm "communication efficient selection": pick two pivots from a
+ * sorted random sample, three-way partition, recurse into the part that holds
+ * rank k) with §4.1's Bernoulli sampling of the current subproblem.
+ *
+ * Problem (§4): identify the elements of rank <= k among n keys.  The order is
+ * made unique by pairing each value with its object (§2, Preliminaries); the
+ * object is the 0-based position of the key (the row-local position in the
+ * batched and row-wise calls), so ties are broken by ascending position.
+ *   - u32 keys: unsigned order.
+ *   - f32 keys: IEEE order with -0.0 == +0.0; every NaN (any sign, any
+ *     payload) equals every other NaN and is above +inf.
+ *   - TOPK_LARGEST reverses the value order; ties still go by ascending
+ *     position.
+ * The result is exact and does not depend on the random sample, which only
+ * steers the running time.
+ *
+ * Conventions for every call below
+ *   - Pointers are device pointers (hipMalloc / torch CUDA tensors) unless
+ *     marked "host".  `keys` is never written.  Outputs and the workspace are
+ *     owned by the caller.  No call allocates device memory.
+ *   - Calls are asynchronous on `stream`: results are valid once the stream
+ *     reaches the call.  Argument errors are reported synchronously by the
+ *     return value and then nothing is enqueued.  Errors found while the
+ *     kernels run are reported in the device `status` word.
+ *   - Keys must be 4-byte aligned; any 4-byte alignment is accepted.
+ *   - A context holds host state only (parameters, seed).  Use one context
+ *     per host thread at a time.  Calls that share a workspace must be
+ *     ordered on one stream.
+ *   - No C++ exception crosses this interface.
+ */
+#ifndef TOPK_H
+#define TOPK_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define TOPK_OK 0
+#define TOPK_E_INVALID (-1)      /* null pointer, n or k out of range, bad flag/param */
+#define TOPK_E_WORKSPACE (-2)    /* ws_bytes smaller than the *_workspace_bytes figure */
+#define TOPK_E_HIP (-3)          /* a HIP runtime call or kernel launch failed */
+#define TOPK_E_UNSUPPORTED (-4)  /* device is not gfx950 */
+
+/* Flags. */
+#define TOPK_LARGEST 1u          /* select the k largest instead of the k smallest  */
+#define TOPK_WRITE_KEYS 4u       /* also write the selected keys (original bits)   */
+#define TOPK_TRACE 8u            /* record every round's sample in the workspace   */
+
+/* Device status word bits (written by every select call when status != NULL). */
+#define TOPK_STATUS_OK 0u
+#define TOPK_STATUS_NO_CONVERGENCE 1u  /* attempt budget r_max spent; outputs invalid */
+#define TOPK_STATUS_BAD_ROW 2u         /* batched: some row had k = 0 or k > len      */
+
+typedef struct topk_ctx topk_ctx;
+
+/* Create a context on HIP device `hip_device` (must be gfx950).  `seed` keys
+ * the counter-based random stream (Philox4x32-10) of the sampler: equal seeds
+ * give equal samples, hence identical traces and output order.
+ * Returns TOPK_OK and *out, TOPK_E_INVALID (out NULL), TOPK_E_HIP or
+ * TOPK_E_UNSUPPORTED. */
+int topk_create(topk_ctx **out, int hip_device, uint64_t seed);
+void topk_destroy(topk_ctx *ctx);
+
+/* Tuning parameters (host).  Names and defaults:
+ *   "s_target"   4096  expected sample size per round (§4.1 samples the
+ *                      current subproblem at rate s_target / n_cur); 16..8192
+ *   "c_num"      16    pivot spread c = c_num / 4; the pivots are the sample
+ *                      elements of rank k s/n -/+ Delta, Delta = ceil(c sqrt(
+ *                      m_hi (s - m_lo) / s)) + 1 (§2, FR-selection); 0..4096
+ *   "t_fin"      8192  subproblems of at most this size are solved directly
+ *                      in one workgroup (§2 base case); 1..16384
+ *   "r_max"      24    attempt budget (rounds + repeated rounds); 1..32
+ *   "r_fast"     -1    multi-workgroup rounds enqueued before the single-
+ *                      workgroup tail; -1 = chosen from n and k; 0..8
+ *   "band_div"   4     the middle part b of a round may hold n/band_div + 65536
+ *                      elements before the round is repeated; 1..64
+ *   "tail_max"   65536 the host's round estimate stops enqueueing multi-
+ *                      workgroup rounds once the expected middle part is below this
+ *   "seed"             the sampler seed (also set by topk_create)
+ * Return TOPK_OK or TOPK_E_INVALID (unknown name / out of range). */
+int topk_set_param(topk_ctx *ctx, const char *name, int64_t value);
+int topk_get_param(const topk_ctx *ctx, const char *name, int64_t *value);
+
+/* Bytes of device workspace a select call on n keys needs with the current
+ * parameters.  The workspace needs no initialisation and may be reused by
+ * later calls ordered on the same stream. */
+size_t topk_workspace_bytes(const topk_ctx *ctx, uint64_t n, uint32_t flags);
+
+/* Select the k smallest (largest with TOPK_LARGEST) of keys[0..n).
+ *   keys      [n]  u32 or f32 keys
+ *   n, k           1 <= k <= n < 2^32
+ *   out_idx   [k]  positions of the selected keys.  Order: the positions
+ *                  below each round's lower pivot, round by round, each run in
+ *                  the order of the round's input (ascending position for the
+ *                  first round), then the remaining selected positions of the
+ *                  final small subproblem in that subproblem's order.  The
+ *                  order is fixed by (keys, k, flags, parameters, seed).
+ *   out_keys  [k]  NULL, or (with TOPK_WRITE_KEYS) keys[out_idx[i]], bits as in
+ *                  the input
+ *   kth_key   [1]  the key of rank k (input bits, e.g. -0.0 and NaN payloads kept)
+ *   kth_idx   [1]  its position; out_idx always contains it
+ *   status    [1]  NULL or the device status word (TOPK_STATUS_*)
+ *   workspace      >= topk_workspace_bytes(ctx, n, flags) bytes, 256-byte aligned
+ * Returns TOPK_OK, TOPK_E_INVALID, TOPK_E_WORKSPACE or TOPK_E_HIP. */
+int topk_select_u32(topk_ctx *ctx, const uint32_t *keys, uint64_t n, uint64_t k,
+                    uint32_t flags, uint32_t *out_idx, uint32_t *out_keys,
+                    uint32_t *kth_key, uint32_t *kth_idx, uint32_t *status,
+                    void *workspace, size_t ws_bytes, hipStream_t stream);
+int topk_select_f32(topk_ctx *ctx, const float *keys, uint64_t n, uint64_t k,
+                    uint32_t flags, uint32_t *out_idx, float *out_keys,
+                    float *kth_key, uint32_t *kth_idx, uint32_t *status,
+                    void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* One recorded round of the last select call that used `workspace`
+ * (§2 Algorithm: sample, pivots l = S[lo] and r = S[hi], counts of a and b). */
+typedef struct topk_round_record {
+    uint32_t n_cur, k_cur;   /* subproblem entering the round                    */
+    uint32_t s;              /* sample size drawn                                 */
+    uint32_t c_num;          /* spread factor used (c = c_num / 4)                */
+    int64_t lo, hi;          /* pivot sample ranks (lo < 0: none; hi >= s: none) */
+    uint32_t l_idx, r_idx;   /* pivot positions in the input (0 when absent)      */
+    uint32_t has_l, has_r;
+    uint32_t na, nb;         /* |a| = #{e < l}, |b| = #{l <= e <= r}               */
+    uint32_t ok;             /* 1: recursed into b; 0: round repeated             */
+    uint32_t tag;            /* attempt number = random stream of the round       */
+} topk_round_record;
+
+/* Copy the round records of the last select call out of `workspace` (device)
+ * into `out` (host, room for `max` records); *count = rounds recorded.
+ * Synchronises `stream`.  With TOPK_TRACE, *_trace_sample copies the sample
+ * positions (indices into that round's input sequence, ascending) of attempt
+ * `tag` into out_pos (host, room for `cap`); *count = sample size. */
+int topk_trace_rounds(const topk_ctx *ctx, const void *workspace, uint64_t n,
+                      topk_round_record *out, uint32_t max, uint32_t *count,
+                      hipStream_t stream);
+int topk_trace_sample(const topk_ctx *ctx, const void *workspace, uint64_t n,
+                      uint32_t tag, uint32_t *out_pos, uint32_t cap, uint32_t *count,
+                      hipStream_t stream);
+
+const char *topk_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TOPK_H */

@@ -1,0 +1,186 @@
+"""MI355X-native unsorted top-k selection (sampling method of Hübschle-Schneider,
+Sanders, Müller, "Communication Efficient Algorithms for Top-k Selection
+Problems", §2 Algorithm "communication efficient selection" and §4.1).
+
+Thin ctypes binding over ``libtopk.so`` (declared in ``include/topk.h``): it
+only marshals torch tensors into pointers, sizes and the current HIP stream.
+Every step of the selection runs in the library's HIP kernels; there is no CPU
+fallback -- a missing library raises.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtopk.so")
+
+TOPK_LARGEST = 1
+TOPK_WRITE_KEYS = 4
+TOPK_TRACE = 8
+STATUS_OK = 0
+STATUS_NO_CONVERGENCE = 1
+STATUS_BAD_ROW = 2
+
+_lib = None
+
+
+class RoundRecord(ctypes.Structure):
+    _fields_ = [
+        ("n_cur", ctypes.c_uint32), ("k_cur", ctypes.c_uint32),
+        ("s", ctypes.c_uint32), ("c_num", ctypes.c_uint32),
+        ("lo", ctypes.c_int64), ("hi", ctypes.c_int64),
+        ("l_idx", ctypes.c_uint32), ("r_idx", ctypes.c_uint32),
+        ("has_l", ctypes.c_uint32), ("has_r", ctypes.c_uint32),
+        ("na", ctypes.c_uint32), ("nb", ctypes.c_uint32),
+        ("ok", ctypes.c_uint32), ("tag", ctypes.c_uint32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class TopkError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libtopk.so (built in-tree by ``__graft_entry__.build()``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise TopkError("libtopk.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u64, u32, i32, sz = (ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                             ctypes.c_int, ctypes.c_size_t)
+    L.topk_create.argtypes = [ctypes.POINTER(vp), i32, u64]
+    L.topk_destroy.argtypes = [vp]
+    L.topk_destroy.restype = None
+    L.topk_set_param.argtypes = [vp, ctypes.c_char_p, ctypes.c_int64]
+    L.topk_get_param.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]
+    L.topk_workspace_bytes.argtypes = [vp, u64, u32]
+    L.topk_workspace_bytes.restype = sz
+    sel = [vp, vp, u64, u64, u32, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.topk_select_u32.argtypes = sel
+    L.topk_select_f32.argtypes = sel
+    L.topk_trace_rounds.argtypes = [vp, vp, u64, ctypes.POINTER(RoundRecord), u32,
+                                    ctypes.POINTER(u32), vp]
+    L.topk_trace_sample.argtypes = [vp, vp, u64, u32, vp, u32, ctypes.POINTER(u32), vp]
+    L.topk_strerror.argtypes = [i32]
+    L.topk_strerror.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        raise TopkError("libtopk: %s (%d)" % (lib().topk_strerror(rc).decode(), rc))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Context:
+    """A libtopk context on one device: tuning parameters and the sampler seed."""
+
+    def __init__(self, device=0, seed=0x5EED):
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        h = ctypes.c_void_p()
+        _check(lib().topk_create(ctypes.byref(h), self.device.index or 0, seed))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.topk_destroy(h)
+            self._h = None
+
+    def set_param(self, name, value):
+        _check(lib().topk_set_param(self._h, name.encode(), int(value)))
+        return self
+
+    def get_param(self, name):
+        v = ctypes.c_int64()
+        _check(lib().topk_get_param(self._h, name.encode(), ctypes.byref(v)))
+        return v.value
+
+    def workspace_bytes(self, n, flags=0):
+        return int(lib().topk_workspace_bytes(self._h, n, flags))
+
+    def workspace(self, n, flags=0):
+        return torch.empty(max(self.workspace_bytes(n, flags), 256), dtype=torch.uint8,
+                           device=self.device)
+
+    def select(self, keys, k, largest=False, write_keys=False, trace=False, workspace=None):
+        """Select the k smallest (or largest) of a 1-D u32/f32 CUDA tensor.
+
+        u32 keys are passed as torch.uint32 or as torch.int32 holding the bits.
+        Returns a dict of device tensors: ``idx`` (int32 holding u32 positions,
+        length k), ``kth_key`` (1 element, dtype of keys), ``kth_idx``,
+        ``status`` and, with ``write_keys``, ``keys``.  ``workspace`` is kept
+        in the dict for trace queries.
+        """
+        if keys.dim() != 1 or not keys.is_cuda:
+            raise ValueError("keys must be a 1-D CUDA tensor")
+        if keys.dtype == torch.float32:
+            fn, is_f32 = lib().topk_select_f32, True
+        elif keys.dtype in (torch.int32, torch.uint32):
+            fn, is_f32 = lib().topk_select_u32, False
+        else:
+            raise TypeError("keys must be float32 or uint32/int32 bits")
+        n = keys.numel()
+        flags = (TOPK_LARGEST if largest else 0) | (TOPK_WRITE_KEYS if write_keys else 0) | \
+                (TOPK_TRACE if trace else 0)
+        dev = keys.device
+        out_idx = torch.empty(max(k, 1), dtype=torch.int32, device=dev)
+        kth_key = torch.empty(1, dtype=keys.dtype, device=dev)
+        kth_idx = torch.empty(1, dtype=torch.int32, device=dev)
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
+        out_keys = torch.empty(max(k, 1), dtype=keys.dtype, device=dev) if write_keys else None
+        if workspace is None:
+            workspace = self.workspace(n, flags)
+        _check(fn(self._h, _ptr(keys), n, k, flags, _ptr(out_idx), _ptr(out_keys),
+                  _ptr(kth_key), _ptr(kth_idx), _ptr(status), _ptr(workspace),
+                  workspace.numel(), _stream(dev)))
+        res = {"idx": out_idx[:k], "kth_key": kth_key, "kth_idx": kth_idx,
+               "status": status, "workspace": workspace, "n": n}
+        if write_keys:
+            res["keys"] = out_keys[:k]
+        return res
+
+    def trace_rounds(self, res):
+        recs = (RoundRecord * 32)()
+        cnt = ctypes.c_uint32()
+        _check(lib().topk_trace_rounds(self._h, _ptr(res["workspace"]), res["n"], recs, 32,
+                                       ctypes.byref(cnt), _stream(res["workspace"].device)))
+        return [recs[i].as_dict() for i in range(min(cnt.value, 32))]
+
+    def trace_sample(self, res, tag):
+        cap = 1 << 16
+        buf = (ctypes.c_uint32 * cap)()
+        cnt = ctypes.c_uint32()
+        _check(lib().topk_trace_sample(self._h, _ptr(res["workspace"]), res["n"], tag, buf, cap,
+                                       ctypes.byref(cnt), _stream(res["workspace"].device)))
+        return list(buf[:min(cnt.value, cap)])
+
+
+_default = {}
+
+
+def default_context(device=None):
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    key = dev.index or 0
+    if key not in _default:
+        _default[key] = Context(key)
+    return _default[key]
+
+
+def select(keys, k, largest=False, write_keys=False):
+    """Top-k selection of a 1-D CUDA tensor with the device's default context."""
+    return default_context(keys.device).select(keys, k, largest=largest, write_keys=write_keys)

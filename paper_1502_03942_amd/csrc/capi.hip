@@ -1,0 +1,299 @@
+// C-ABI of libtopk: context, parameters, workspace layout, argument checks and
+// the launch plan of the single-instance selection.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <new>
+
+#include "../../include/topk.h"
+#include "select.hpp"
+
+using namespace topk;
+
+struct topk_ctx {
+    int device;
+    uint64_t seed;
+    int64_t s_target, c_num, t_fin, r_max, r_fast, band_div, tail_max;
+    int num_cu;
+};
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x, size_t a = ALIGN) { return (x + a - 1) / a * a; }
+
+struct Layout {
+    size_t state, stat, band[4], trace, total;
+    uint32_t ntiles_max, band_cap, band_alloc;
+};
+
+Layout make_layout(const topk_ctx *c, uint64_t n, uint32_t flags)
+{
+    Layout L{};
+    size_t off = 0;
+    L.state = off;
+    off = align_up(off + sizeof(State));
+    L.ntiles_max = (uint32_t)((n + 3 + SW_TILE - 1) / SW_TILE);
+    L.stat = off;
+    off = align_up(off + (size_t)4 * L.ntiles_max * sizeof(uint64_t));
+    uint64_t cap = n / (uint64_t)c->band_div + 65536;
+    if (cap > n) cap = n;
+    if (n <= (uint64_t)c->t_fin) cap = 0;
+    L.band_cap = (uint32_t)cap;
+    L.band_alloc = (uint32_t)((cap + SW_TILE - 1) / SW_TILE * SW_TILE);
+    for (int i = 0; i < 4; ++i) {
+        L.band[i] = off;
+        off = align_up(off + (size_t)L.band_alloc * sizeof(uint32_t));
+    }
+    L.trace = off;
+    if (flags & TOPK_TRACE) off = align_up(off + (size_t)R_TRACE * TRACE_STRIDE * sizeof(uint32_t));
+    L.total = off;
+    return L;
+}
+
+// Pivot ranks, as in the device code; used only for the host's round estimate.
+void est_ranks(uint64_t s, uint64_t k, uint64_t n, uint64_t c_num, int64_t &lo, int64_t &hi)
+{
+    const uint64_t m_lo = k * s / n, m_hi = (k * s + n - 1) / n;
+    const double d = ceil((double)c_num / 4.0 * sqrt((double)m_hi * (double)(s - m_lo) / (double)s));
+    lo = (int64_t)m_lo - (int64_t)d - 1;
+    hi = (int64_t)m_hi + (int64_t)d + 1;
+}
+
+// Expected subproblem sizes of the multi-workgroup rounds: the band of a
+// round holds about (hi - lo) / s of the round's input.
+int plan_rounds(const topk_ctx *c, uint64_t n, uint64_t k, double *sizes, int max_r)
+{
+    int r = 0;
+    double nr = (double)n, kr = (double)k;
+    while (r < max_r && nr > (double)c->t_fin) {
+        sizes[r++] = nr;
+        const double s = nr < (double)c->s_target ? nr : (double)c->s_target;
+        int64_t lo, hi;
+        uint64_t ki = (uint64_t)(kr < 1 ? 1 : kr), ni = (uint64_t)nr;
+        if (ki > ni) ki = ni;
+        est_ranks((uint64_t)s, ki, ni, (uint64_t)c->c_num, lo, hi);
+        const double flo = lo > 0 ? (double)lo / s : 0.0;
+        const double fhi = hi + 1 < (int64_t)s ? (double)(hi + 1) / s : 1.0;
+        const double nb = (fhi - flo) * nr;
+        kr -= flo * nr;
+        nr = nb;
+        if (nr <= (double)c->tail_max) break;
+    }
+    return r;
+}
+
+int check_device(int device, int *num_cu)
+{
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, device) != hipSuccess) return TOPK_E_HIP;
+    if (strncmp(p.gcnArchName, "gfx950", 6) != 0) return TOPK_E_UNSUPPORTED;
+    *num_cu = p.multiProcessorCount;
+    return TOPK_OK;
+}
+
+template <typename K>
+int select_common(topk_ctx *c, const K *keys, uint64_t n, uint64_t k, uint32_t flags,
+                  uint32_t *out_idx, uint32_t *out_keys, uint32_t *kth_key,
+                  uint32_t *kth_idx, uint32_t *status, void *ws, size_t ws_bytes,
+                  hipStream_t stream, bool is_f32)
+{
+    if (!c || !keys || !out_idx || !kth_key || !kth_idx || !ws) return TOPK_E_INVALID;
+    if (n == 0 || k == 0 || k > n || n > 0xFFFFFFFFull) return TOPK_E_INVALID;
+    if (flags & ~(TOPK_LARGEST | TOPK_WRITE_KEYS | TOPK_TRACE)) return TOPK_E_INVALID;
+    if ((flags & TOPK_WRITE_KEYS) && !out_keys) return TOPK_E_INVALID;
+    if (((uintptr_t)keys & 3u) || ((uintptr_t)ws & (ALIGN - 1))) return TOPK_E_INVALID;
+    const Layout L = make_layout(c, n, flags);
+    if (ws_bytes < L.total) return TOPK_E_WORKSPACE;
+    char *w = (char *)ws;
+    SelArgs a{};
+    a.keys = (const uint32_t *)keys;
+    a.mis = (uint32_t)(((uintptr_t)keys & 15u) >> 2);
+    a.n = (uint32_t)n;
+    a.k = (uint32_t)k;
+    a.flags = flags;
+    a.out_idx = out_idx;
+    a.out_keys = (flags & TOPK_WRITE_KEYS) ? out_keys : nullptr;
+    a.kth_key = kth_key;
+    a.kth_idx = kth_idx;
+    a.status = status;
+    a.st = (State *)(w + L.state);
+    a.stat = (uint64_t *)(w + L.stat);
+    a.ntiles_max = L.ntiles_max;
+    a.band_cap = L.band_cap;
+    a.band_ord[0] = (uint32_t *)(w + L.band[0]);
+    a.band_idx[0] = (uint32_t *)(w + L.band[1]);
+    a.band_ord[1] = (uint32_t *)(w + L.band[2]);
+    a.band_idx[1] = (uint32_t *)(w + L.band[3]);
+    a.trace_pos = (flags & TOPK_TRACE) ? (uint32_t *)(w + L.trace) : nullptr;
+    a.s_target = (uint32_t)c->s_target;
+    a.c_num0 = (uint32_t)c->c_num;
+    a.t_fin = (uint32_t)c->t_fin;
+    a.r_max = (uint32_t)c->r_max;
+    a.seed = c->seed;
+    a.clear_words = 2 * L.ntiles_max;
+
+    SelLaunch P{};
+    P.is_f32 = is_f32;
+    P.largest = (flags & TOPK_LARGEST) != 0;
+    double sizes[8];
+    int r = plan_rounds(c, n, k, sizes, 8);
+    if (c->r_fast >= 0) r = (int)c->r_fast;
+    P.r_fast = r;
+    const int gmax = c->num_cu * 8;
+    for (int i = 0; i < 8; ++i) {
+        // round i's expected input, with slack; rounds beyond the plan get the
+        // full grid (they only run after a repeated round)
+        const double ni = (i == 0 || i >= r) ? (double)n : sizes[i] * 1.25 + SW_TILE;
+        const uint64_t t = (uint64_t)ceil(ni / SW_TILE) + 1;
+        P.sweep_grid[i] = (int)(t < (uint64_t)gmax ? t : (uint64_t)gmax);
+    }
+    P.clear_blocks = (int)((a.clear_words + PV_THREADS * 8 - 1) / (PV_THREADS * 8));
+    if (hipSetDevice(c->device) != hipSuccess) return TOPK_E_HIP;
+    return launch_select(a, P, stream) == hipSuccess ? TOPK_OK : TOPK_E_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int topk_create(topk_ctx **out, int hip_device, uint64_t seed)
+{
+    if (!out) return TOPK_E_INVALID;
+    *out = nullptr;
+    int ncu = 0;
+    int rc = check_device(hip_device, &ncu);
+    if (rc != TOPK_OK) return rc;
+    topk_ctx *c = new (std::nothrow) topk_ctx;
+    if (!c) return TOPK_E_INVALID;
+    c->device = hip_device;
+    c->seed = seed;
+    c->s_target = 4096;
+    c->c_num = 16;
+    c->t_fin = 8192;
+    c->r_max = 24;
+    c->r_fast = -1;
+    c->band_div = 4;
+    c->tail_max = 65536;
+    c->num_cu = ncu;
+    *out = c;
+    return TOPK_OK;
+}
+
+void topk_destroy(topk_ctx *c) { delete c; }
+
+int topk_set_param(topk_ctx *c, const char *name, int64_t v)
+{
+    if (!c || !name) return TOPK_E_INVALID;
+    struct { const char *n; int64_t *p; int64_t lo, hi; } tab[] = {
+        {"s_target", &c->s_target, 16, 8192},
+        {"c_num", &c->c_num, 0, 4096},
+        {"t_fin", &c->t_fin, 1, T_FIN_MAX},
+        {"r_max", &c->r_max, 1, R_TRACE},
+        {"r_fast", &c->r_fast, -1, 8},
+        {"band_div", &c->band_div, 1, 64},
+        {"tail_max", &c->tail_max, 0, (int64_t)1 << 32},
+    };
+    if (strcmp(name, "seed") == 0) { c->seed = (uint64_t)v; return TOPK_OK; }
+    for (auto &e : tab) {
+        if (strcmp(name, e.n) == 0) {
+            if (v < e.lo || v > e.hi) return TOPK_E_INVALID;
+            *e.p = v;
+            return TOPK_OK;
+        }
+    }
+    return TOPK_E_INVALID;
+}
+
+int topk_get_param(const topk_ctx *c, const char *name, int64_t *v)
+{
+    if (!c || !name || !v) return TOPK_E_INVALID;
+    if (strcmp(name, "seed") == 0) { *v = (int64_t)c->seed; return TOPK_OK; }
+    const struct { const char *n; int64_t val; } tab[] = {
+        {"s_target", c->s_target}, {"c_num", c->c_num}, {"t_fin", c->t_fin},
+        {"r_max", c->r_max}, {"r_fast", c->r_fast}, {"band_div", c->band_div},
+        {"tail_max", c->tail_max},
+    };
+    for (auto &e : tab) {
+        if (strcmp(name, e.n) == 0) { *v = e.val; return TOPK_OK; }
+    }
+    return TOPK_E_INVALID;
+}
+
+size_t topk_workspace_bytes(const topk_ctx *c, uint64_t n, uint32_t flags)
+{
+    if (!c) return 0;
+    return make_layout(c, n, flags).total;
+}
+
+int topk_select_u32(topk_ctx *c, const uint32_t *keys, uint64_t n, uint64_t k,
+                    uint32_t flags, uint32_t *out_idx, uint32_t *out_keys,
+                    uint32_t *kth_key, uint32_t *kth_idx, uint32_t *status,
+                    void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    return select_common(c, keys, n, k, flags, out_idx, out_keys, kth_key, kth_idx,
+                         status, ws, ws_bytes, stream, false);
+}
+
+int topk_select_f32(topk_ctx *c, const float *keys, uint64_t n, uint64_t k,
+                    uint32_t flags, uint32_t *out_idx, float *out_keys,
+                    float *kth_key, uint32_t *kth_idx, uint32_t *status,
+                    void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    return select_common(c, keys, n, k, flags, out_idx, (uint32_t *)out_keys,
+                         (uint32_t *)kth_key, kth_idx, status, ws, ws_bytes, stream, true);
+}
+
+int topk_trace_rounds(const topk_ctx *c, const void *ws, uint64_t n,
+                      topk_round_record *out, uint32_t max, uint32_t *count,
+                      hipStream_t stream)
+{
+    (void)n;
+    if (!c || !ws || !out || !count) return TOPK_E_INVALID;
+    static_assert(sizeof(RoundRec) == sizeof(topk_round_record), "record layout");
+    State st;
+    if (hipMemcpyAsync(&st, ws, sizeof(State), hipMemcpyDeviceToHost, stream) != hipSuccess)
+        return TOPK_E_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return TOPK_E_HIP;
+    uint32_t m = st.nrec < (uint32_t)R_TRACE ? st.nrec : (uint32_t)R_TRACE;
+    if (m > max) m = max;
+    memcpy(out, st.rec, m * sizeof(RoundRec));
+    *count = st.nrec;
+    return TOPK_OK;
+}
+
+int topk_trace_sample(const topk_ctx *c, const void *ws, uint64_t n, uint32_t tag,
+                      uint32_t *out_pos, uint32_t cap, uint32_t *count, hipStream_t stream)
+{
+    if (!c || !ws || !out_pos || !count || tag >= (uint32_t)R_TRACE) return TOPK_E_INVALID;
+    const Layout L = make_layout(c, n, TOPK_TRACE);
+    State st;
+    if (hipMemcpyAsync(&st, ws, sizeof(State), hipMemcpyDeviceToHost, stream) != hipSuccess)
+        return TOPK_E_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return TOPK_E_HIP;
+    if (tag >= st.nrec) { *count = 0; return TOPK_OK; }
+    uint32_t s = st.rec[tag].s;
+    *count = s;
+    if (s > cap) s = cap;
+    const char *src = (const char *)ws + L.trace + (size_t)tag * TRACE_STRIDE * sizeof(uint32_t);
+    if (hipMemcpyAsync(out_pos, src, (size_t)s * sizeof(uint32_t), hipMemcpyDeviceToHost, stream) != hipSuccess)
+        return TOPK_E_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return TOPK_E_HIP;
+    return TOPK_OK;
+}
+
+const char *topk_strerror(int code)
+{
+    switch (code) {
+    case TOPK_OK: return "ok";
+    case TOPK_E_INVALID: return "invalid argument";
+    case TOPK_E_WORKSPACE: return "workspace too small";
+    case TOPK_E_HIP: return "HIP runtime error";
+    case TOPK_E_UNSUPPORTED: return "device is not gfx950";
+    default: return "unknown error";
+    }
+}
+
+}  // extern "C"

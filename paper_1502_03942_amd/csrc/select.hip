@@ -1,0 +1,749 @@
+// Single-instance sampling selection (Hübschle-Schneider, Sanders, Müller):
+// §2 Algorithm "communication efficient selection" with §4.1's Bernoulli
+// sampling, mapped onto one gfx950 device.
+//
+//   k_pivot  one 1024-thread workgroup: applies the branch of the Algorithm to
+//            the counts of the previous sweep (driver), then either solves a
+//            small subproblem directly (finisher) or draws the Bernoulli sample
+//            of the current subproblem (geometric skips, §2) and picks the two
+//            pivots by an LDS radix select of two sample ranks.
+//   k_sweep  many workgroups: one streaming pass over the subproblem that
+//            classifies every element against (l, r), counts a and b with
+//            wave ballots, turns the per-tile counts into global offsets with a
+//            single-pass decoupled look-back scan (Merrill & Garland 2016), and
+//            writes a's positions to the output and b to the next band buffer
+//            in sequence order.
+//   k_tail   one workgroup that runs the remaining rounds itself (driver,
+//            sample, pivots, a workgroup-wide sweep) and the finisher.
+//
+// The host enqueues k_pivot, k_sweep, [k_pivot, k_sweep]..., k_tail once; the
+// round state lives in device memory, so no round trip to the host occurs.
+#include "common.hpp"
+#include "select.hpp"
+#include "../../include/topk.h"
+
+namespace topk {
+
+typedef u32 u32x4 __attribute__((ext_vector_type(4)));
+
+struct Smem {
+    u32 hist[2][256];
+    u32 scan[PV_THREADS / WAVE];
+    u32 sel_bin[2], sel_before[2], sel_count[2];
+    u64 found[2];
+    u64 L64, R64;
+    i64 lo, hi;
+    u32 phase, n_cur, k_cur, src, tag, c_num, cursor, s_total;
+};
+
+// ---------------------------------------------------------------------------
+// Radix select in one workgroup.  Every thread holds up to M keys in registers
+// (the first `cnt` valid).  Finds the keys of 0-based ranks rank[0] and rank[1]
+// (each only if act[t]) among all valid keys, most significant byte first:
+// histogram the next byte of the keys that share the prefix found so far,
+// locate the byte that holds the rank, narrow, stop as soon as a bucket holds
+// one key.  Keys must be distinct (they are (ord, position) pairs).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void hist_add(u32 *h, int d)
+{
+    const u64 act = ballot(d >= 0);
+    if (act == 0) return;
+    const int fl = __ffsll((unsigned long long)act) - 1;
+    const int dl = __shfl(d, fl, WAVE);
+    const u64 same = ballot(d == dl);
+    if ((int)lane_id() == fl) atomicAdd(&h[dl], (u32)__popcll(same));
+    if (d >= 0 && d != dl) atomicAdd(&h[d], 1u);
+}
+
+template <int M>
+__device__ void radix_select(const u64 (&v)[M], int cnt, const u64 rank_in[2],
+                             const bool act[2], u64 out[2], Smem &sm)
+{
+    const u32 tid = threadIdx.x;
+    u64 prefix[2] = {0ull, 0ull};
+    u64 rank[2] = {rank_in[0], rank_in[1]};
+    bool uniq[2] = {false, false};
+    int ushift[2] = {0, 0};
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        const bool need0 = act[0] && !uniq[0];
+        const bool need1 = act[1] && !uniq[1];
+        if (!need0 && !need1) break;
+        for (u32 i = tid; i < 512; i += PV_THREADS) (&sm.hist[0][0])[i] = 0u;
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            if (t == 0 ? need0 : need1) {
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    const bool m = j < cnt &&
+                        (shift == 56 || ((v[j] ^ prefix[t]) >> (shift + 8)) == 0);
+                    const int d = m ? (int)((v[j] >> shift) & 255u) : -1;
+                    hist_add(sm.hist[t], d);
+                }
+            }
+        }
+        __syncthreads();
+        const u32 w = tid / WAVE;
+        if (w < 2 && (w == 0 ? need0 : need1)) {
+            const u32 l = lane_id();
+            const u32 c0 = sm.hist[w][4 * l], c1 = sm.hist[w][4 * l + 1];
+            const u32 c2 = sm.hist[w][4 * l + 2], c3 = sm.hist[w][4 * l + 3];
+            const u32 tot = c0 + c1 + c2 + c3;
+            u64 before = wave_incl_scan(tot) - tot;
+            const u64 r = rank[w];
+            const u32 c[4] = {c0, c1, c2, c3};
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                if (before <= r && r < before + c[b]) {
+                    sm.sel_bin[w] = 4 * l + b;
+                    sm.sel_before[w] = (u32)before;
+                    sm.sel_count[w] = c[b];
+                }
+                before += c[b];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            if (t == 0 ? need0 : need1) {
+                prefix[t] |= (u64)sm.sel_bin[t] << shift;
+                rank[t] -= sm.sel_before[t];
+                if (sm.sel_count[t] == 1u) { uniq[t] = true; ushift[t] = shift; }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        if (act[t]) {
+#pragma unroll
+            for (int j = 0; j < M; ++j)
+                if (j < cnt && ((v[j] ^ prefix[t]) >> ushift[t]) == 0) sm.found[t] = v[j];
+        }
+    }
+    __syncthreads();
+    out[0] = sm.found[0];
+    out[1] = sm.found[1];
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Pivot ranks (§2, FR-selection: sample ranks k|S|/n -/+ Delta).  Integer form
+// of Delta = ceil(c sqrt(m_hi (s - m_lo) / s)) + 1 with c = c_num / 4:
+// the least D with 16 s D^2 >= c_num^2 m_hi (s - m_lo).
+// ---------------------------------------------------------------------------
+__device__ void pivot_ranks(u64 s, u64 k, u64 n, u32 c_num, i64 &lo, i64 &hi)
+{
+    if (s == 0) { lo = -1; hi = 0; return; }
+    const u64 m_lo = k * s / n;
+    const u64 m_hi = (k * s + n - 1) / n;
+    const u64 X = (u64)c_num * c_num * m_hi * (s - m_lo);
+    const u64 Y = 16 * s;
+    const u64 t = (X + Y - 1) / Y;
+    u64 d = (u64)sqrt((double)t);
+    while (d * d < t) ++d;
+    while (d > 0 && (d - 1) * (d - 1) >= t) --d;
+    lo = (i64)m_lo - (i64)(d + 1);
+    hi = (i64)m_hi + (i64)(d + 1);
+}
+
+// ---------------------------------------------------------------------------
+// State machine pieces (thread 0 of the driving workgroup).
+// ---------------------------------------------------------------------------
+__device__ void state_init(const SelArgs &a, State *st)
+{
+    st->phase = PH_PIVOT;
+    st->n_cur = a.n;
+    st->k_cur = a.k;
+    st->cursor = 0;
+    st->src = 0;
+    st->tag = 0;
+    st->c_num = a.c_num0;
+    st->ticket = 0;
+    st->na = st->nb = 0;
+    st->nrec = 0;
+}
+
+// Branch of the Algorithm after a sweep: recurse into b when the pivots
+// bracket rank k_cur (n_a < k_cur <= n_a + n_b); otherwise (the Algorithm's
+// recursions into a or c, a band larger than its buffer, or no progress)
+// repeat the round on the same subproblem with a fresh stream and c doubled.
+__device__ void driver_eval(const SelArgs &a, State *st)
+{
+    if (st->phase != PH_SWEEP) return;
+    const u32 tag = st->tag, na = st->na, nb = st->nb;
+    const u32 n = st->n_cur, k = st->k_cur;
+    const bool ok = !(na >= k || (u64)na + nb < k || nb > a.band_cap || nb == n);
+    if (tag < R_TRACE) {
+        st->rec[tag].na = na;
+        st->rec[tag].nb = nb;
+        st->rec[tag].ok = ok ? 1u : 0u;
+    }
+    st->tag = tag + 1;
+    if (ok) {
+        st->cursor += na;
+        st->k_cur = k - na;
+        st->n_cur = nb;
+        st->src = (st->src == 1) ? 2u : 1u;
+        st->c_num = a.c_num0;
+    } else {
+        const u32 c = st->c_num * 2u;
+        st->c_num = c > 4096u ? 4096u : c;
+    }
+    st->phase = PH_PIVOT;
+}
+
+__device__ __forceinline__ void load_state(const State *st, Smem &sm)
+{
+    sm.phase = st->phase;
+    sm.n_cur = st->n_cur;
+    sm.k_cur = st->k_cur;
+    sm.src = st->src;
+    sm.tag = st->tag;
+    sm.c_num = st->c_num;
+    sm.cursor = st->cursor;
+}
+
+// element `p` of the current subproblem as an (ord, position) pair
+template <bool IS_F32, bool LARGEST>
+__device__ __forceinline__ u64 fetch_elem(const SelArgs &a, u32 src, u64 p)
+{
+    if (src == 0) return pack(key_ord<IS_F32, LARGEST>(a.keys[p]), (u32)p);
+    return pack(a.band_ord[src - 1][p], a.band_idx[src - 1][p]);
+}
+
+// ---------------------------------------------------------------------------
+// Sample and pivots (§2 "Bernoulli sampling", FR-selection; §4.1 samples the
+// current subproblem at rate s_target / n_cur).  Thread t owns segment t of
+// ceil(n/1024) consecutive positions and walks it with geometric skips
+// 1 + floor(ln U / ln(1 - rho)), U from Philox4x32-10 counter
+// (draw/4, t, attempt, 0) and key = seed; it keeps at most SEG_CAP positions.
+// ---------------------------------------------------------------------------
+template <bool IS_F32, bool LARGEST>
+__device__ void sample_and_pivot(const SelArgs &a, State *st, Smem &sm)
+{
+    const u32 tid = threadIdx.x;
+    const u32 n = sm.n_cur, k = sm.k_cur, src = sm.src, tag = sm.tag;
+    const double rho = (double)a.s_target / (double)n;
+    const u64 L = ((u64)n + NSEG - 1) / NSEG;
+    const u64 s0 = (u64)tid * L;
+    const u64 e0 = s0 + L < (u64)n ? s0 + L : (u64)n;
+    u32 pos[SEG_CAP];
+    int cnt = 0;
+    if (s0 < e0) {
+        if (rho >= 1.0) {
+#pragma unroll
+            for (int j = 0; j < SEG_CAP; ++j)
+                if (s0 + j < e0) { pos[j] = (u32)(s0 + j); cnt = j + 1; }
+        } else {
+            const double ln1mrho = log1p(-rho);
+            i64 p = (i64)s0 - 1;
+            bool stop = false;
+            uint4 r4 = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+            for (int j = 0; j < SEG_CAP; ++j) {
+                if (!stop) {
+                    if ((j & 3) == 0)
+                        r4 = philox4x32_10(make_uint4((u32)(j >> 2), tid, tag, 0u),
+                                           (u32)a.seed, (u32)(a.seed >> 32));
+                    const u32 w = (j & 3) == 0 ? r4.x : (j & 3) == 1 ? r4.y
+                                : (j & 3) == 2 ? r4.z : r4.w;
+                    const double u = ((double)w + 0.5) * (1.0 / 4294967296.0);
+                    const double q = log(u) / ln1mrho;
+                    if (q >= (double)((i64)e0 - 1 - p)) {
+                        stop = true;
+                    } else {
+                        p = p + 1 + (i64)q;
+                        pos[j] = (u32)p;
+                        cnt = j + 1;
+                    }
+                }
+            }
+        }
+    }
+    u64 v[SEG_CAP];
+#pragma unroll
+    for (int j = 0; j < SEG_CAP; ++j)
+        v[j] = j < cnt ? fetch_elem<IS_F32, LARGEST>(a, src, pos[j]) : ~0ull;
+
+    u32 s_total;
+    const u32 excl = block_excl_scan<PV_THREADS>((u32)cnt, sm.scan, &s_total);
+    if (a.trace_pos && tag < R_TRACE) {
+        u32 *tp = a.trace_pos + (u64)tag * TRACE_STRIDE + excl;
+#pragma unroll
+        for (int j = 0; j < SEG_CAP; ++j)
+            if (j < cnt) tp[j] = pos[j];
+    }
+    if (tid == 0) {
+        i64 lo, hi;
+        pivot_ranks(s_total, k, n, sm.c_num, lo, hi);
+        sm.lo = lo;
+        sm.hi = hi;
+        sm.s_total = s_total;
+    }
+    __syncthreads();
+    const i64 lo = sm.lo, hi = sm.hi;
+    const bool act[2] = {lo >= 0, hi < (i64)s_total};
+    const u64 ranks[2] = {act[0] ? (u64)lo : 0ull, act[1] ? (u64)hi : 0ull};
+    u64 piv[2];
+    radix_select<SEG_CAP>(v, cnt, ranks, act, piv, sm);
+    if (tid == 0) {
+        const u64 Lp = act[0] ? piv[0] : 0ull;
+        const u64 Rp = act[1] ? piv[1] : ~0ull;
+        sm.L64 = Lp;
+        sm.R64 = Rp;
+        st->l_ord = (u32)(Lp >> 32);
+        st->l_idx = (u32)Lp;
+        st->r_ord = (u32)(Rp >> 32);
+        st->r_idx = (u32)Rp;
+        st->has_l = act[0];
+        st->has_r = act[1];
+        if (tag < R_TRACE) {
+            RoundRec &R = st->rec[tag];
+            R.n_cur = n; R.k_cur = k; R.s = s_total; R.c_num = sm.c_num;
+            R.lo = lo; R.hi = hi;
+            R.l_idx = act[0] ? (u32)Lp : 0u;
+            R.r_idx = act[1] ? (u32)Rp : 0u;
+            R.has_l = act[0]; R.has_r = act[1];
+            R.na = R.nb = R.ok = 0u;
+            R.tag = tag;
+            st->nrec = tag + 1;
+        }
+        st->ticket = 0;
+        st->phase = PH_SWEEP;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Finisher (§2 base case): a subproblem of n_cur <= t_fin elements is loaded
+// into registers (thread t holds a run of consecutive positions), tau = its
+// element of rank k_cur is found by radix select, and every element <= tau is
+// written in sequence order after the cursor.
+// ---------------------------------------------------------------------------
+template <bool IS_F32, bool LARGEST>
+__device__ void finish(const SelArgs &a, State *st, Smem &sm)
+{
+    const u32 tid = threadIdx.x;
+    const u32 n = sm.n_cur, k = sm.k_cur, src = sm.src;
+    const u32 per = (n + PV_THREADS - 1) / PV_THREADS;
+    const u64 b0 = (u64)tid * per;
+    const int cnt = b0 >= n ? 0 : (int)((u64)n - b0 < per ? (u64)n - b0 : per);
+    u64 v[FIN_ITEMS];
+#pragma unroll
+    for (int j = 0; j < FIN_ITEMS; ++j)
+        v[j] = j < cnt ? fetch_elem<IS_F32, LARGEST>(a, src, b0 + j) : ~0ull;
+    const u64 ranks[2] = {(u64)k - 1, 0ull};
+    const bool act[2] = {true, false};
+    u64 tau2[2];
+    radix_select<FIN_ITEMS>(v, cnt, ranks, act, tau2, sm);
+    const u64 tau = tau2[0];
+    u32 c = 0;
+#pragma unroll
+    for (int j = 0; j < FIN_ITEMS; ++j) c += (j < cnt && v[j] <= tau) ? 1u : 0u;
+    u32 tot;
+    u32 off = block_excl_scan<PV_THREADS>(c, sm.scan, &tot);
+    const u64 base = (u64)sm.cursor + off;
+    const bool wkeys = (a.flags & TOPK_WRITE_KEYS) && a.out_keys;
+    u32 m = 0;
+#pragma unroll
+    for (int j = 0; j < FIN_ITEMS; ++j) {
+        if (j < cnt && v[j] <= tau) {
+            const u32 idx = (u32)v[j];
+            if (base + m < a.k) {
+                a.out_idx[base + m] = idx;
+                if (wkeys) a.out_keys[base + m] = a.keys[idx];
+            }
+            ++m;
+        }
+        if (j < cnt && v[j] == tau) {
+            const u32 idx = (u32)v[j];
+            *a.kth_idx = idx;
+            *a.kth_key = a.keys[idx];
+        }
+    }
+    if (tid == 0) {
+        st->phase = PH_DONE;
+        if (a.status) *a.status = (tot == k) ? TOPK_STATUS_OK : TOPK_STATUS_NO_CONVERGENCE;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup-wide sweep for the tail kernel: the same partition as k_sweep,
+// done by one workgroup in order, with a running offset instead of look-back.
+// ---------------------------------------------------------------------------
+template <bool IS_F32, bool LARGEST>
+__device__ void block_sweep(const SelArgs &a, State *st, Smem &sm)
+{
+    const u32 tid = threadIdx.x;
+    const u32 n = sm.n_cur, src = sm.src;
+    const u32 di = (src == 1) ? 1u : 0u;     // destination band buffer
+    const u64 L64 = sm.L64, R64 = sm.R64;
+    const bool wkeys = (a.flags & TOPK_WRITE_KEYS) && a.out_keys;
+    u64 run_a = 0, run_b = 0;
+    for (u64 base = 0; base < n; base += (u64)PV_THREADS * 4) {
+        u64 e[4];
+        bool fa[4], fb[4];
+        u32 ta = 0, tb = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const u64 p = base + (u64)tid * 4 + u;
+            const bool valid = p < n;
+            e[u] = valid ? fetch_elem<IS_F32, LARGEST>(a, src, p) : 0ull;
+            const bool below = e[u] < L64;
+            const bool above = e[u] > R64;
+            fa[u] = valid && below;
+            fb[u] = valid && !below && !above;
+            ta += fa[u];
+            tb += fb[u];
+        }
+        u32 tot;
+        const u32 ex = block_excl_scan<PV_THREADS>(ta | (tb << 16), sm.scan, &tot);
+        u64 pa = (u64)sm.cursor + run_a + (ex & 0xFFFFu);
+        u64 pb = run_b + (ex >> 16);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const u32 idx = (u32)e[u];
+            if (fa[u]) {
+                if (pa < a.k) {
+                    a.out_idx[pa] = idx;
+                    if (wkeys) a.out_keys[pa] = a.keys[idx];
+                }
+                ++pa;
+            }
+            if (fb[u]) {
+                if (pb < a.band_cap) {
+                    a.band_ord[di][pb] = (u32)(e[u] >> 32);
+                    a.band_idx[di][pb] = idx;
+                }
+                ++pb;
+            }
+        }
+        run_a += tot & 0xFFFFu;
+        run_b += tot >> 16;
+    }
+    if (tid == 0) {
+        st->na = (u32)run_a;
+        st->nb = (u32)run_b;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Kernels.
+// ---------------------------------------------------------------------------
+template <bool IS_F32, bool LARGEST>
+__global__ __launch_bounds__(PV_THREADS) void k_pivot(SelArgs a)
+{
+    if (blockIdx.x > 0) {
+        // first kernel of a call: clear the parity-0 look-back status words
+        const u64 per = (u64)PV_THREADS * 8;
+        const u64 i0 = (u64)(blockIdx.x - 1) * per;
+        for (u64 i = i0 + threadIdx.x; i < i0 + per && i < a.clear_words; i += PV_THREADS)
+            a.stat[i] = 0ull;
+        return;
+    }
+    __shared__ Smem sm;
+    State *st = a.st;
+    if (threadIdx.x == 0) {
+        if (a.first) state_init(a, st);
+        driver_eval(a, st);
+        load_state(st, sm);
+    }
+    __syncthreads();
+    if (sm.phase != PH_PIVOT) return;
+    if (sm.n_cur <= a.t_fin) {
+        finish<IS_F32, LARGEST>(a, st, sm);
+        return;
+    }
+    if (sm.tag >= a.r_max) {
+        if (threadIdx.x == 0) {
+            st->phase = PH_ERROR;
+            if (a.status) *a.status = TOPK_STATUS_NO_CONVERGENCE;
+        }
+        return;
+    }
+    sample_and_pivot<IS_F32, LARGEST>(a, st, sm);
+}
+
+template <bool IS_F32, bool LARGEST>
+__global__ __launch_bounds__(PV_THREADS) void k_tail(SelArgs a)
+{
+    __shared__ Smem sm;
+    State *st = a.st;
+    bool first = a.first != 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            if (first) state_init(a, st);
+            driver_eval(a, st);
+            load_state(st, sm);
+        }
+        first = false;
+        __syncthreads();
+        if (sm.phase != PH_PIVOT) return;
+        if (sm.n_cur <= a.t_fin) {
+            finish<IS_F32, LARGEST>(a, st, sm);
+            return;
+        }
+        if (sm.tag >= a.r_max) {
+            if (threadIdx.x == 0) {
+                st->phase = PH_ERROR;
+                if (a.status) *a.status = TOPK_STATUS_NO_CONVERGENCE;
+            }
+            return;
+        }
+        sample_and_pivot<IS_F32, LARGEST>(a, st, sm);
+        block_sweep<IS_F32, LARGEST>(a, st, sm);
+    }
+}
+
+// Single-pass look-back (run by wave 0): publish the tile's counts (flag 1),
+// add predecessors' counts 64 tiles at a time until a tile with an inclusive
+// prefix (flag 2) is met, publish this tile's inclusive prefix.  Status word =
+// flag << 32 | value, cleared to 0 before the sweep.
+__device__ void lookback(u64 *sa, u64 *sb, u32 tile, u32 agg_a, u32 agg_b,
+                         u32 &ex_a, u32 &ex_b)
+{
+    constexpr u64 F_AGG = 1ull << 32, F_INC = 2ull << 32;
+    const u32 l = lane_id();
+    if (tile == 0) {
+        if (l == 0) {
+            st_status(&sa[0], F_INC | agg_a);
+            st_status(&sb[0], F_INC | agg_b);
+        }
+        ex_a = ex_b = 0;
+        return;
+    }
+    if (l == 0) {
+        st_status(&sa[tile], F_AGG | agg_a);
+        st_status(&sb[tile], F_AGG | agg_b);
+    }
+    u32 ea = 0, eb = 0;
+    bool da = false, db = false;
+    i64 pred = (i64)tile - 1;
+    while (!(da && db)) {
+        const i64 t = pred - (i64)l;
+        u64 wa = F_INC, wb = F_INC;
+        if (t >= 0) {
+            for (;;) {
+                if (!da) wa = ld_status(&sa[t]);
+                if (!db) wb = ld_status(&sb[t]);
+                if ((wa >> 32) != 0 && (wb >> 32) != 0) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        if (!da) {
+            const u64 inc = ballot((wa >> 32) == 2);
+            const u32 val = (u32)wa;
+            if (inc) {
+                const int f = __ffsll((unsigned long long)inc) - 1;
+                ea += wave_sum_u32((int)l <= f ? val : 0u);
+                da = true;
+            } else {
+                ea += wave_sum_u32(val);
+            }
+        }
+        if (!db) {
+            const u64 inc = ballot((wb >> 32) == 2);
+            const u32 val = (u32)wb;
+            if (inc) {
+                const int f = __ffsll((unsigned long long)inc) - 1;
+                eb += wave_sum_u32((int)l <= f ? val : 0u);
+                db = true;
+            } else {
+                eb += wave_sum_u32(val);
+            }
+        }
+        pred -= WAVE;
+    }
+    if (l == 0) {
+        st_status(&sa[tile], F_INC | (u64)(ea + agg_a));
+        st_status(&sb[tile], F_INC | (u64)(eb + agg_b));
+    }
+    ex_a = ea;
+    ex_b = eb;
+}
+
+// The hot loop (§2 Algorithm's partition and reduction; §10 notes that the
+// partition dominates the running time).  A tile is 4 chunks of 1024
+// consecutive elements; in chunk j thread t holds elements 4t..4t+3, loaded
+// with one 128-bit load.  Tiles are taken in order from an atomic ticket, so
+// every tile a look-back waits for belongs to a running workgroup.
+template <bool IS_F32, bool LARGEST>
+__global__ __launch_bounds__(SW_THREADS) void k_sweep(SelArgs a)
+{
+    constexpr int NW = SW_THREADS / WAVE;
+    constexpr int CH = SW_ITEMS / 4;
+    State *st = a.st;
+    if (st->phase != PH_SWEEP) return;
+    const u32 n = st->n_cur, src = st->src, tag = st->tag;
+    const u32 mis = src == 0 ? a.mis : 0u;
+    const u32 ntiles = (u32)(((u64)n + mis + SW_TILE - 1) / SW_TILE);
+    if (blockIdx.x >= ntiles) return;
+    const u64 L64 = st->has_l ? pack(st->l_ord, st->l_idx) : 0ull;
+    const u64 R64 = st->has_r ? pack(st->r_ord, st->r_idx) : ~0ull;
+    const u64 cursor = st->cursor;
+    u64 *sa = a.stat + (u64)(tag & 1u) * 2 * a.ntiles_max;
+    u64 *sb = sa + a.ntiles_max;
+    u64 *nx = a.stat + (u64)((tag + 1u) & 1u) * 2 * a.ntiles_max;
+    const u32 di = (src == 1) ? 1u : 0u;
+    u32 *__restrict__ dord = a.band_ord[di];
+    u32 *__restrict__ didx = a.band_idx[di];
+    const u32 *__restrict__ sord = src ? a.band_ord[src - 1] : nullptr;
+    const u32 *__restrict__ sidx = src ? a.band_idx[src - 1] : nullptr;
+    const u32 *__restrict__ kbase = a.keys - mis;
+    const bool wkeys = (a.flags & TOPK_WRITE_KEYS) && a.out_keys;
+    const u32 tid = threadIdx.x, w = tid / WAVE;
+
+    __shared__ u32 s_tile;
+    __shared__ u32 s_w[CH][NW];
+    __shared__ u32 s_ex[2];
+
+    for (;;) {
+        if (tid == 0) s_tile = atomicAdd(&st->ticket, 1u);
+        __syncthreads();
+        const u32 tile = s_tile;
+        if (tile >= ntiles) break;
+        if (tid == 0) {
+            nx[tile] = 0ull;
+            nx[a.ntiles_max + tile] = 0ull;
+        }
+        u32 ord[SW_ITEMS], idx[SW_ITEMS], bits[SW_ITEMS];
+        u32 fa = 0, fb = 0;   // bit (4j+u): element (j,u) is in a / in b
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const u64 q0 = (u64)tile * SW_TILE + (u64)j * (SW_THREADS * 4) + (u64)tid * 4;
+            if (src == 0) {
+                u32x4 x = {0u, 0u, 0u, 0u};
+                if (q0 < (u64)n + mis)
+                    x = __builtin_nontemporal_load((const u32x4 *)(kbase + q0));
+                bits[4 * j + 0] = x.x; bits[4 * j + 1] = x.y;
+                bits[4 * j + 2] = x.z; bits[4 * j + 3] = x.w;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    ord[4 * j + u] = key_ord<IS_F32, LARGEST>(bits[4 * j + u]);
+                    idx[4 * j + u] = (u32)(q0 + u - mis);
+                }
+            } else {
+                u32x4 o = {0u, 0u, 0u, 0u}, x = {0u, 0u, 0u, 0u};
+                if (q0 < (u64)n) {
+                    o = __builtin_nontemporal_load((const u32x4 *)(sord + q0));
+                    x = __builtin_nontemporal_load((const u32x4 *)(sidx + q0));
+                }
+                ord[4 * j + 0] = o.x; ord[4 * j + 1] = o.y; ord[4 * j + 2] = o.z; ord[4 * j + 3] = o.w;
+                idx[4 * j + 0] = x.x; idx[4 * j + 1] = x.y; idx[4 * j + 2] = x.z; idx[4 * j + 3] = x.w;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const u64 vp = q0 + u;
+                const bool valid = vp >= mis && vp < (u64)n + mis;
+                const u64 e = pack(ord[4 * j + u], idx[4 * j + u]);
+                const bool below = e < L64;
+                const bool above = e > R64;
+                fa |= (u32)(valid && below) << (4 * j + u);
+                fb |= (u32)(valid && !below && !above) << (4 * j + u);
+            }
+        }
+        // per chunk: wave counts and this lane's prefix within the wave
+        u32 lpa[CH], lpb[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            u32 ta = 0, tb = 0, pa = 0, pb = 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const u64 ba = ballot((fa >> (4 * j + u)) & 1u);
+                const u64 bb = ballot((fb >> (4 * j + u)) & 1u);
+                pa += mbcnt(ba);
+                pb += mbcnt(bb);
+                ta += (u32)__popcll(ba);
+                tb += (u32)__popcll(bb);
+            }
+            lpa[j] = pa;
+            lpb[j] = pb;
+            if (lane_id() == 0) s_w[j][w] = ta | (tb << 16);
+        }
+        __syncthreads();
+        u32 basep[CH], tot = 0;
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            u32 bw = 0, cj = 0;
+#pragma unroll
+            for (int x = 0; x < NW; ++x) {
+                const u32 c = s_w[j][x];
+                bw += (x < (int)w) ? c : 0u;
+                cj += c;
+            }
+            basep[j] = tot + bw;
+            tot += cj;
+        }
+        if (w == 0) {
+            u32 ea, eb;
+            lookback(sa, sb, tile, tot & 0xFFFFu, tot >> 16, ea, eb);
+            if (lane_id() == 0) {
+                s_ex[0] = ea;
+                s_ex[1] = eb;
+                if (tile == ntiles - 1) {
+                    st->na = ea + (tot & 0xFFFFu);
+                    st->nb = eb + (tot >> 16);
+                }
+            }
+        }
+        __syncthreads();
+        const u64 ex_a = s_ex[0], ex_b = s_ex[1];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            u64 pa = cursor + ex_a + (basep[j] & 0xFFFFu) + lpa[j];
+            u64 pb = ex_b + (basep[j] >> 16) + lpb[j];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = 4 * j + u;
+                if ((fa >> i) & 1u) {
+                    if (pa < a.k) {
+                        a.out_idx[pa] = idx[i];
+                        if (wkeys) a.out_keys[pa] = src == 0 ? bits[i] : a.keys[idx[i]];
+                    }
+                    ++pa;
+                }
+                if ((fb >> i) & 1u) {
+                    if (pb < a.band_cap) {
+                        dord[pb] = ord[i];
+                        didx[pb] = idx[i];
+                    }
+                    ++pb;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+template <bool F, bool LG>
+static hipError_t launch_impl(SelArgs a, const SelLaunch &L, hipStream_t s)
+{
+    a.first = 1;
+    if (a.n <= a.t_fin || L.r_fast <= 0) {
+        hipLaunchKernelGGL((k_tail<F, LG>), dim3(1), dim3(PV_THREADS), 0, s, a);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_pivot<F, LG>), dim3(1 + L.clear_blocks), dim3(PV_THREADS), 0, s, a);
+    a.first = 0;
+    for (int r = 0; r < L.r_fast; ++r) {
+        hipLaunchKernelGGL((k_sweep<F, LG>), dim3(L.sweep_grid[r]), dim3(SW_THREADS), 0, s, a);
+        if (r + 1 < L.r_fast)
+            hipLaunchKernelGGL((k_pivot<F, LG>), dim3(1), dim3(PV_THREADS), 0, s, a);
+    }
+    hipLaunchKernelGGL((k_tail<F, LG>), dim3(1), dim3(PV_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const SelArgs &a, const SelLaunch &L, hipStream_t stream)
+{
+    if (L.is_f32) {
+        return L.largest ? launch_impl<true, true>(a, L, stream)
+                         : launch_impl<true, false>(a, L, stream);
+    }
+    return L.largest ? launch_impl<false, true>(a, L, stream)
+                     : launch_impl<false, false>(a, L, stream);
+}
+
+}  // namespace topk

@@ -1,0 +1,63 @@
+// Host/device declarations of the single-instance selection path.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace topk {
+
+constexpr int PV_THREADS = 1024;               // sample/pivot, finisher, tail workgroup
+constexpr int SEG_CAP = 16;                    // samples kept per sampler segment
+constexpr int NSEG = PV_THREADS;               // sampler segments (one per thread)
+constexpr int FIN_ITEMS = 16;                  // finisher keys per thread
+constexpr int T_FIN_MAX = PV_THREADS * FIN_ITEMS;
+constexpr int SW_THREADS = 256;                // multi-workgroup sweep
+constexpr int SW_ITEMS = 16;                   // keys per thread per tile
+constexpr int SW_TILE = SW_THREADS * SW_ITEMS; // 4096 keys per tile
+constexpr int R_TRACE = 32;                    // attempt records kept
+constexpr int TRACE_STRIDE = NSEG * SEG_CAP;   // sample positions per record
+
+enum : uint32_t { PH_PIVOT = 0, PH_SWEEP = 1, PH_DONE = 2, PH_ERROR = 3 };
+
+struct RoundRec {                 // same layout as topk_round_record
+    uint32_t n_cur, k_cur, s, c_num;
+    int64_t lo, hi;
+    uint32_t l_idx, r_idx, has_l, has_r;
+    uint32_t na, nb, ok, tag;
+};
+
+struct State {
+    uint32_t phase, n_cur, k_cur, cursor;
+    uint32_t src, tag, c_num, ticket;
+    uint32_t na, nb, nrec, pad0;
+    uint32_t l_ord, l_idx, r_ord, r_idx;
+    uint32_t has_l, has_r, pad1, pad2;
+    RoundRec rec[R_TRACE];
+};
+
+struct SelArgs {
+    const uint32_t *keys;       // input key bits
+    uint32_t mis;               // keys - 16-byte-aligned base, in elements (0..3)
+    uint32_t n, k, flags;
+    uint32_t *out_idx, *out_keys, *kth_key, *kth_idx, *status;
+    State *st;
+    uint64_t *stat;             // [2 parities][2 (a,b)][ntiles_max]
+    uint32_t ntiles_max;
+    uint32_t band_cap;
+    uint32_t *band_ord[2], *band_idx[2];
+    uint32_t *trace_pos;        // [R_TRACE][TRACE_STRIDE] or nullptr
+    uint32_t s_target, c_num0, t_fin, r_max;
+    uint64_t seed;
+    uint32_t first;             // first kernel of the call: initialise the state
+    uint32_t clear_words;       // first pivot kernel: status words of parity 0 to clear
+};
+
+struct SelLaunch {
+    int is_f32, largest;
+    int r_fast;                 // multi-workgroup rounds before the tail kernel
+    int sweep_grid[8];          // workgroups per enqueued sweep
+    int clear_blocks;
+};
+
+hipError_t launch_select(const SelArgs &a, const SelLaunch &L, hipStream_t stream);
+
+}  // namespace topk
