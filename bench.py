@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Throughput of the sampling top-k selection on one MI355X.
+
+One step = select the k smallest of n = 2^28 fp32 keys (uniform on [0,1) at
+2^-24 resolution, seeded, resident in HBM) for each k in {2^10, 2^20, 2^27}.
+Prints one JSON line on stdout; progress goes to stderr.
+
+  value        whole-step keys processed per second (3 * 2^28 keys per step)
+  roofline     the dominant kernel (the first-round sweep): algorithmic bytes
+               per launch (4 B read per key + 4 B per position written below
+               the lower pivot + 8 B per (ord, position) pair written to the
+               band) divided by its average duration, both measured here with
+               HIP events on the library's stream during the timed steps
+  cpu_baseline the CPU oracle (full sort by (value, position), one thread) on a
+               bounded sample of the same workload
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Gkeys/s and % HBM roofline, top-k select n=2^28 fp32; batched vs per-row loop"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def traffic_record(kernel):
+    """Measured HBM bytes per launch from a committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, "paper_1502_03942_amd", "csrc", "select.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec
+
+
+def bench_select(args):
+    import torch
+    import paper_1502_03942_amd as tk
+    import synth
+
+    n = 1 << 28
+    ks = (1 << 10, 1 << 20, 1 << 27)
+    dev = torch.device("cuda:0")
+    log("generating %d f32 keys" % n)
+    keys_np = synth.uniform_f32_grid(n, 2)
+    keys = torch.from_numpy(keys_np).to(dev)
+    ctx = tk.Context(0, seed=0x5EED)
+    ws = {k: ctx.workspace(n) for k in ks}
+    ctx.set_param("timing", 1)
+    results = {}
+
+    def step():
+        for k in ks:
+            results[k] = ctx.select(keys, k, workspace=ws[k])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.kernel_times()                        # drop warm-up records
+    log("warmup done; timing %d steps" % args.steps)
+    per_k_ms = {k: 0.0 for k in ks}
+    # whole-step time: events on the stream the library launches on
+    stream = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    ek = [torch.cuda.Event(enable_timing=True) for _ in range(len(ks) + 1)]
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        for i, k in enumerate(ks):
+            results[k] = ctx.select(keys, k, workspace=ws[k])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    kt = ctx.kernel_times()
+    sweeps = [ms for kind, ms in kt if kind == "sweep_first"]
+    assert len(sweeps) == args.steps * len(ks), (len(sweeps), args.steps)
+    # per-k whole-call times (separate short pass, same launches)
+    for i, k in enumerate(ks):
+        ek[0].record(stream)
+        for _ in range(args.steps):
+            ctx.select(keys, k, workspace=ws[k])
+        ek[1].record(stream)
+        torch.cuda.synchronize()
+        per_k_ms[k] = ek[0].elapsed_time(ek[1]) / args.steps
+    ctx.kernel_times()
+
+    ms_per_step = total_ms / args.steps
+    value = len(ks) * n / (ms_per_step * 1e-3) / 1e9
+
+    # algorithmic bytes of each k's first sweep, from its round record
+    sweep_bytes = {}
+    per_k = []
+    for k in ks:
+        recs = ctx.trace_rounds(results[k])
+        r0 = recs[0]
+        sweep_bytes[k] = 4 * n + 4 * r0["na"] + 8 * r0["nb"]
+        b_min = 4 * n + 4 * k
+        per_k.append({
+            "k": k, "ms": round(per_k_ms[k], 4),
+            "gkeys_s": round(n / (per_k_ms[k] * 1e-3) / 1e9, 2),
+            "hbm_frac_min_bytes": round(b_min / (per_k_ms[k] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "rounds": len(recs), "band1": r0["nb"], "below1": r0["na"],
+        })
+    # sweeps are in enqueue order: step-major, k-minor
+    tot_bytes = sum(sweep_bytes[ks[i % len(ks)]] for i in range(len(sweeps)))
+    tot_s = sum(sweeps) * 1e-3
+    achieved = tot_bytes / tot_s / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_sweep<first round>",
+            "avg_launch_ms": round(sum(sweeps) / len(sweeps), 5),
+            "algorithmic_bytes_per_launch": round(tot_bytes / len(sweeps))}
+    tr = traffic_record("sweep_first")
+    if tr is not None:
+        roof["traffic"] = tr["bytes_per_launch"]
+
+    if not args.no_check:
+        import oracle
+        for k in ks:
+            r = results[k]
+            got = r["idx"].cpu().numpy().view(np.uint32)
+            kth = int(r["kth_idx"].item())
+            kb = int(r["kth_key"].cpu().numpy().view(np.uint32)[0])
+            rc = oracle.check(keys_np, k, got, kth, kb, False)
+            log("check k=%d: %s" % (k, "ok" if rc == 0 else "FAILED invariant %d" % rc))
+            if rc != 0 or int(r["status"].item()) != 0:
+                raise SystemExit("result check failed for k=%d" % k)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        m = 1 << 23
+        sample = keys_np[:m]
+        ks_s = [max(1, k * m // n) for k in ks]
+        log("cpu baseline: oracle on %d keys" % m)
+        t0 = time.perf_counter()
+        for k in ks_s:
+            oracle.select_sort(sample, k)
+        dt = time.perf_counter() - t0
+        model, ncpu = cpu_info()
+        cpu = {"value": round(len(ks_s) * m / dt / 1e9, 5), "unit": "Gkeys/s", "cores": 1,
+               "kind": "oracle",
+               "sample": "first 2^23 keys of the same array, k scaled by 2^-5 to %s; full sort "
+                         "by (value, position) per k, one thread; %.1f s; host %s (%d logical CPUs)"
+                         % (ks_s, dt, model, ncpu)}
+
+    return {
+        "metric": METRIC, "value": round(value, 2), "unit": "Gkeys/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "select smallest k of n=2^28 f32 keys uniform on [0,1) "
+                               "(2^-24 grid, seed 2), k in {2^10, 2^20, 2^27}, one step = "
+                               "the three selections", "n": n, "k": list(ks),
+                   "parallelism": "none (1 GPU)"},
+        "per_k": per_k, "roofline": roof, "cpu_baseline": cpu,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the selection runs on a single device "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    out = bench_select(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

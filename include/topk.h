@@ -86,6 +86,8 @@ void topk_destroy(topk_ctx *ctx);
  *                      elements before the round is repeated; 1..64
  *   "tail_max"   65536 the host's round estimate stops enqueueing multi-
  *                      workgroup rounds once the expected middle part is below this
+ *   "timing"     0     1: record HIP events around each call's first sweep
+ *                      kernel; 2: around every kernel (see topk_kernel_times)
  *   "seed"             the sampler seed (also set by topk_create)
  * Return TOPK_OK or TOPK_E_INVALID (unknown name / out of range). */
 int topk_set_param(topk_ctx *ctx, const char *name, int64_t value);
@@ -146,6 +148,14 @@ int topk_trace_rounds(const topk_ctx *ctx, const void *workspace, uint64_t n,
 int topk_trace_sample(const topk_ctx *ctx, const void *workspace, uint64_t n,
                       uint32_t tag, uint32_t *out_pos, uint32_t cap, uint32_t *count,
                       hipStream_t stream);
+
+/* Kernel durations recorded (with parameter "timing" > 0) by the calls since
+ * the last read-out, in enqueue order: ms[i] (milliseconds between HIP events
+ * recorded on the call's stream just before and after the kernel) and
+ * kind[i] (0 first pivot kernel, 1 pivot kernel, 2 first-round sweep,
+ * 3 later sweep, 4 tail kernel).  Waits for the events; clears the record.
+ * *count = kernels recorded (only min(count, max) are written). */
+int topk_kernel_times(topk_ctx *ctx, float *ms, int32_t *kind, uint32_t max, uint32_t *count);
 
 const char *topk_strerror(int code);
 

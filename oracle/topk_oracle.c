@@ -292,11 +292,13 @@ void orc_pivot_ranks(uint64_t s, uint64_t k, uint64_t n, uint32_t c_num,
  * into a = {e < l}, b = {l <= e <= r}, c = {e > r}; n_a = |a|, n_b = |b|.
  * Elements of a are written (in sequence order) to out_idx after the
  * `cursor` elements already fixed; b (in sequence order) becomes the next
- * subproblem; k_cur -= n_a.  A round whose pivots do not bracket rank k_cur
- * (n_a >= k_cur or n_a + n_b < k_cur), whose b exceeds band_cap, or that
- * makes no progress (n_b = n_cur) is repeated on the same subproblem with a
- * fresh random stream and c doubled (this replaces the recursion into a or c;
- * the result is the same).  Once n_cur <= t_fin the subproblem is solved
+ * subproblem; k_cur -= n_a.  A round is repeated on the same subproblem with
+ * a fresh random stream when its pivots do not bracket rank k_cur (n_a >=
+ * k_cur or n_a + n_b < k_cur; this replaces the recursion into a or c, with
+ * the same result) -- then with c doubled -- or when b is too wide (more
+ * than band_cap elements, or n_b = n_cur: no progress) -- then with c halved.
+ * After a recursion into b, c returns to its initial value.  Once
+ * n_cur <= t_fin the subproblem is solved
  * directly: tau = its element of rank k_cur; every element <= tau (in sequence
  * order) is written after the cursor.  More than r_max rounds: status 1.
  *
@@ -378,7 +380,9 @@ int orc_replay(const void *keys, int is_f32, uint64_t n, uint64_t k, int largest
                 ++nb;
             }
         }
-        int ok = !(na >= k_cur || na + nb < k_cur || nb > prm->band_cap || nb == n_cur);
+        int miss = na >= k_cur || na + nb < k_cur;
+        int wide = nb > prm->band_cap || nb == n_cur;
+        int ok = !miss && !wide;
         if (recs) {
             orc_round *R = &recs[nr];
             R->n_cur = (uint32_t)n_cur; R->k_cur = (uint32_t)k_cur; R->s = (uint32_t)s;
@@ -388,8 +392,12 @@ int orc_replay(const void *keys, int is_f32, uint64_t n, uint64_t k, int largest
         }
         ++nr;
         ++tag;
-        if (!ok) {
+        if (miss) {
             c_num = c_num * 2 > 4096 ? 4096 : c_num * 2;
+            continue;
+        }
+        if (wide) {
+            c_num = c_num / 2;
             continue;
         }
         cursor += na;

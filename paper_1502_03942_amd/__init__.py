@@ -67,6 +67,7 @@ def lib():
     L.topk_trace_rounds.argtypes = [vp, vp, u64, ctypes.POINTER(RoundRecord), u32,
                                     ctypes.POINTER(u32), vp]
     L.topk_trace_sample.argtypes = [vp, vp, u64, u32, vp, u32, ctypes.POINTER(u32), vp]
+    L.topk_kernel_times.argtypes = [vp, vp, vp, u32, ctypes.POINTER(u32)]
     L.topk_strerror.argtypes = [i32]
     L.topk_strerror.restype = ctypes.c_char_p
     _lib = L
@@ -153,6 +154,17 @@ class Context:
         if write_keys:
             res["keys"] = out_keys[:k]
         return res
+
+    KERNEL_KINDS = ("pivot_first", "pivot", "sweep_first", "sweep", "tail")
+
+    def kernel_times(self, max_records=1 << 16):
+        """Durations (ms) of the kernels recorded with param "timing" > 0 since
+        the last read-out, as a list of (kind, ms) in enqueue order."""
+        ms = (ctypes.c_float * max_records)()
+        kind = (ctypes.c_int32 * max_records)()
+        cnt = ctypes.c_uint32()
+        _check(lib().topk_kernel_times(self._h, ms, kind, max_records, ctypes.byref(cnt)))
+        return [(self.KERNEL_KINDS[kind[i]], ms[i]) for i in range(min(cnt.value, max_records))]
 
     def trace_rounds(self, res):
         recs = (RoundRecord * 32)()

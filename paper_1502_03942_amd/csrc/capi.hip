@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "../../include/topk.h"
 #include "select.hpp"
@@ -15,8 +16,12 @@ using namespace topk;
 struct topk_ctx {
     int device;
     uint64_t seed;
-    int64_t s_target, c_num, t_fin, r_max, r_fast, band_div, tail_max;
+    int64_t s_target, c_num, t_fin, r_max, r_fast, band_div, tail_max, timing;
     int num_cu;
+    // kernel timing: event pairs recorded by calls since the last read-out
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_kind;
+    int ev_used = 0;
 };
 
 namespace {
@@ -152,7 +157,26 @@ int select_common(topk_ctx *c, const K *keys, uint64_t n, uint64_t k, uint32_t f
     }
     P.clear_blocks = (int)((a.clear_words + PV_THREADS * 8 - 1) / (PV_THREADS * 8));
     if (hipSetDevice(c->device) != hipSuccess) return TOPK_E_HIP;
-    return launch_select(a, P, stream) == hipSuccess ? TOPK_OK : TOPK_E_HIP;
+    KernelTimer tm{};
+    if (c->timing > 0) {
+        const int need = c->ev_used + 2 * P.r_fast + 4;
+        while ((int)c->ev_kind.size() < need) {
+            hipEvent_t e0, e1;
+            if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+                return TOPK_E_HIP;
+            c->ev.push_back(e0);
+            c->ev.push_back(e1);
+            c->ev_kind.push_back(-1);
+        }
+        tm.level = (int)c->timing;
+        tm.ev = c->ev.data();
+        tm.kind = c->ev_kind.data();
+        tm.cap = (int)c->ev_kind.size();
+        tm.used = c->ev_used;
+    }
+    const hipError_t e = launch_select(a, P, stream, c->timing > 0 ? &tm : nullptr);
+    if (c->timing > 0) c->ev_used = tm.used;
+    return e == hipSuccess ? TOPK_OK : TOPK_E_HIP;
 }
 
 }  // namespace
@@ -177,12 +201,18 @@ int topk_create(topk_ctx **out, int hip_device, uint64_t seed)
     c->r_fast = -1;
     c->band_div = 4;
     c->tail_max = 65536;
+    c->timing = 0;
     c->num_cu = ncu;
     *out = c;
     return TOPK_OK;
 }
 
-void topk_destroy(topk_ctx *c) { delete c; }
+void topk_destroy(topk_ctx *c)
+{
+    if (!c) return;
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    delete c;
+}
 
 int topk_set_param(topk_ctx *c, const char *name, int64_t v)
 {
@@ -195,6 +225,7 @@ int topk_set_param(topk_ctx *c, const char *name, int64_t v)
         {"r_fast", &c->r_fast, -1, 8},
         {"band_div", &c->band_div, 1, 64},
         {"tail_max", &c->tail_max, 0, (int64_t)1 << 32},
+        {"timing", &c->timing, 0, 2},
     };
     if (strcmp(name, "seed") == 0) { c->seed = (uint64_t)v; return TOPK_OK; }
     for (auto &e : tab) {
@@ -214,7 +245,7 @@ int topk_get_param(const topk_ctx *c, const char *name, int64_t *v)
     const struct { const char *n; int64_t val; } tab[] = {
         {"s_target", c->s_target}, {"c_num", c->c_num}, {"t_fin", c->t_fin},
         {"r_max", c->r_max}, {"r_fast", c->r_fast}, {"band_div", c->band_div},
-        {"tail_max", c->tail_max},
+        {"tail_max", c->tail_max}, {"timing", c->timing},
     };
     for (auto &e : tab) {
         if (strcmp(name, e.n) == 0) { *v = e.val; return TOPK_OK; }
@@ -281,6 +312,22 @@ int topk_trace_sample(const topk_ctx *c, const void *ws, uint64_t n, uint32_t ta
     if (hipMemcpyAsync(out_pos, src, (size_t)s * sizeof(uint32_t), hipMemcpyDeviceToHost, stream) != hipSuccess)
         return TOPK_E_HIP;
     if (hipStreamSynchronize(stream) != hipSuccess) return TOPK_E_HIP;
+    return TOPK_OK;
+}
+
+int topk_kernel_times(topk_ctx *c, float *ms, int32_t *kind, uint32_t max, uint32_t *count)
+{
+    if (!c || !count || (max && (!ms || !kind))) return TOPK_E_INVALID;
+    const uint32_t m = (uint32_t)c->ev_used;
+    for (uint32_t i = 0; i < m && i < max; ++i) {
+        if (hipEventSynchronize(c->ev[2 * i + 1]) != hipSuccess) return TOPK_E_HIP;
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, c->ev[2 * i], c->ev[2 * i + 1]) != hipSuccess) return TOPK_E_HIP;
+        ms[i] = t;
+        kind[i] = c->ev_kind[i];
+    }
+    *count = m;
+    c->ev_used = 0;
     return TOPK_OK;
 }
 

@@ -165,15 +165,18 @@ __device__ void state_init(const SelArgs &a, State *st)
 }
 
 // Branch of the Algorithm after a sweep: recurse into b when the pivots
-// bracket rank k_cur (n_a < k_cur <= n_a + n_b); otherwise (the Algorithm's
-// recursions into a or c, a band larger than its buffer, or no progress)
-// repeat the round on the same subproblem with a fresh stream and c doubled.
+// bracket rank k_cur (n_a < k_cur <= n_a + n_b) and b is narrower than its
+// buffer and than the subproblem.  Otherwise repeat the round on the same
+// subproblem with a fresh stream: after a miss (the Algorithm's recursions
+// into a or c) with c doubled, after a too wide b with c halved.
 __device__ void driver_eval(const SelArgs &a, State *st)
 {
     if (st->phase != PH_SWEEP) return;
     const u32 tag = st->tag, na = st->na, nb = st->nb;
     const u32 n = st->n_cur, k = st->k_cur;
-    const bool ok = !(na >= k || (u64)na + nb < k || nb > a.band_cap || nb == n);
+    const bool miss = na >= k || (u64)na + nb < k;
+    const bool wide = nb > a.band_cap || nb == n;
+    const bool ok = !miss && !wide;
     if (tag < R_TRACE) {
         st->rec[tag].na = na;
         st->rec[tag].nb = nb;
@@ -186,9 +189,11 @@ __device__ void driver_eval(const SelArgs &a, State *st)
         st->n_cur = nb;
         st->src = (st->src == 1) ? 2u : 1u;
         st->c_num = a.c_num0;
-    } else {
+    } else if (miss) {
         const u32 c = st->c_num * 2u;
         st->c_num = c > 4096u ? 4096u : c;
+    } else {
+        st->c_num = st->c_num / 2u;
     }
     st->phase = PH_PIVOT;
 }
@@ -568,8 +573,10 @@ __device__ void lookback(u64 *sa, u64 *sb, u32 tile, u32 agg_a, u32 agg_b,
 // partition dominates the running time).  A tile is 4 chunks of 1024
 // consecutive elements; in chunk j thread t holds elements 4t..4t+3, loaded
 // with one 128-bit load.  Tiles are taken in order from an atomic ticket, so
-// every tile a look-back waits for belongs to a running workgroup.
-template <bool IS_F32, bool LARGEST>
+// every tile a look-back waits for belongs to a running workgroup.  FIRST only
+// names the instance enqueued for the first round (which always reads the
+// input) apart from later rounds' instances in profiles.
+template <bool IS_F32, bool LARGEST, bool FIRST>
 __global__ __launch_bounds__(SW_THREADS) void k_sweep(SelArgs a)
 {
     constexpr int NW = SW_THREADS / WAVE;
@@ -717,33 +724,66 @@ __global__ __launch_bounds__(SW_THREADS) void k_sweep(SelArgs a)
 }
 
 // ---------------------------------------------------------------------------
+static int tm_begin(KernelTimer *tm, int kind, hipStream_t s)
+{
+    if (!tm || tm->level == 0 || tm->used >= tm->cap) return -1;
+    if (tm->level == 1 && kind != KT_SWEEP_FIRST) return -1;
+    const int i = tm->used++;
+    tm->kind[i] = kind;
+    (void)hipEventRecord(tm->ev[2 * i], s);
+    return i;
+}
+
+static void tm_end(KernelTimer *tm, int i, hipStream_t s)
+{
+    if (i >= 0) (void)hipEventRecord(tm->ev[2 * i + 1], s);
+}
+
 template <bool F, bool LG>
-static hipError_t launch_impl(SelArgs a, const SelLaunch &L, hipStream_t s)
+static hipError_t launch_impl(SelArgs a, const SelLaunch &L, hipStream_t s, KernelTimer *tm)
 {
     a.first = 1;
+    int t;
     if (a.n <= a.t_fin || L.r_fast <= 0) {
+        t = tm_begin(tm, KT_TAIL, s);
         hipLaunchKernelGGL((k_tail<F, LG>), dim3(1), dim3(PV_THREADS), 0, s, a);
+        tm_end(tm, t, s);
         return hipGetLastError();
     }
+    t = tm_begin(tm, KT_PIVOT_FIRST, s);
     hipLaunchKernelGGL((k_pivot<F, LG>), dim3(1 + L.clear_blocks), dim3(PV_THREADS), 0, s, a);
+    tm_end(tm, t, s);
     a.first = 0;
     for (int r = 0; r < L.r_fast; ++r) {
-        hipLaunchKernelGGL((k_sweep<F, LG>), dim3(L.sweep_grid[r]), dim3(SW_THREADS), 0, s, a);
-        if (r + 1 < L.r_fast)
+        if (r == 0) {
+            t = tm_begin(tm, KT_SWEEP_FIRST, s);
+            hipLaunchKernelGGL((k_sweep<F, LG, true>), dim3(L.sweep_grid[r]), dim3(SW_THREADS), 0, s, a);
+        } else {
+            t = tm_begin(tm, KT_SWEEP, s);
+            hipLaunchKernelGGL((k_sweep<F, LG, false>), dim3(L.sweep_grid[r]), dim3(SW_THREADS), 0, s, a);
+        }
+        tm_end(tm, t, s);
+        if (r + 1 < L.r_fast) {
+            t = tm_begin(tm, KT_PIVOT, s);
             hipLaunchKernelGGL((k_pivot<F, LG>), dim3(1), dim3(PV_THREADS), 0, s, a);
+            tm_end(tm, t, s);
+        }
     }
+    t = tm_begin(tm, KT_TAIL, s);
     hipLaunchKernelGGL((k_tail<F, LG>), dim3(1), dim3(PV_THREADS), 0, s, a);
+    tm_end(tm, t, s);
     return hipGetLastError();
 }
 
-hipError_t launch_select(const SelArgs &a, const SelLaunch &L, hipStream_t stream)
+hipError_t launch_select(const SelArgs &a, const SelLaunch &L, hipStream_t stream,
+                         KernelTimer *tm)
 {
     if (L.is_f32) {
-        return L.largest ? launch_impl<true, true>(a, L, stream)
-                         : launch_impl<true, false>(a, L, stream);
+        return L.largest ? launch_impl<true, true>(a, L, stream, tm)
+                         : launch_impl<true, false>(a, L, stream, tm);
     }
-    return L.largest ? launch_impl<false, true>(a, L, stream)
-                     : launch_impl<false, false>(a, L, stream);
+    return L.largest ? launch_impl<false, true>(a, L, stream, tm)
+                     : launch_impl<false, false>(a, L, stream, tm);
 }
 
 }  // namespace topk

@@ -58,6 +58,16 @@ struct SelLaunch {
     int clear_blocks;
 };
 
-hipError_t launch_select(const SelArgs &a, const SelLaunch &L, hipStream_t stream);
+// Optional HIP-event timing of the enqueued kernels (start/stop event pairs).
+enum : int { KT_PIVOT_FIRST = 0, KT_PIVOT = 1, KT_SWEEP_FIRST = 2, KT_SWEEP = 3, KT_TAIL = 4 };
+struct KernelTimer {
+    int level;          // 0: off, 1: first sweep only, 2: every kernel
+    hipEvent_t *ev;     // [2 * cap]
+    int *kind;          // [cap]
+    int cap, used;
+};
+
+hipError_t launch_select(const SelArgs &a, const SelLaunch &L, hipStream_t stream,
+                         KernelTimer *tm);
 
 }  // namespace topk

@@ -371,6 +371,29 @@ def test_replay_rounds_and_output_layout():
     assert recs[0]["ok"] and np.all(np.diff(out[:na1].astype(np.int64)) > 0)
 
 
+def test_replay_wide_band_halves_spread():
+    # s_target = 16 at the median: Delta >= s/2 with c = 4, so b is the whole
+    # subproblem; halving c restores progress
+    keys = synth.small_alphabet_u32(20000, 5, 4)
+    rc, out, kth, recs = oracle.replay(keys, 10000, s_target=16, c_num=16, nseg=1024,
+                                       seg_cap=16, t_fin=64, r_max=32, band_cap=20000, seed=5)
+    assert rc == 0
+    assert not recs[0]["ok"] and recs[0]["nb"] == recs[0]["n_cur"]
+    assert recs[1]["c_num"] == 8
+    ref = oracle.select_sort(keys, 10000)
+    assert np.array_equal(np.sort(out), np.sort(ref)) and kth == ref[-1]
+
+
+def test_replay_miss_doubles_spread():
+    keys = synth.uniform_u32(300000, 9)
+    rc, out, kth, recs = oracle.replay(keys, 77, s_target=256, c_num=0, nseg=1024,
+                                       seg_cap=16, t_fin=512, r_max=32, band_cap=300000, seed=3)
+    assert rc == 0
+    for a, b in zip(recs, recs[1:]):
+        if not a["ok"] and (a["na"] >= a["k_cur"] or a["na"] + a["nb"] < a["k_cur"]):
+            assert b["c_num"] == min(2 * a["c_num"], 4096)
+
+
 def test_replay_band_cap_overflow_and_budget():
     keys = synth.uniform_u32(50000, 5)
     prm = dict(s_target=64, c_num=16, nseg=16, seg_cap=16, t_fin=64, r_max=6)

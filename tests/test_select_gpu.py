@@ -145,10 +145,28 @@ def test_band_overflow_and_no_convergence(dev):
 
 
 def test_small_t_fin_and_sample(dev):
+    # s_target = 16 leaves b as wide as the subproblem near the median until
+    # the spread c has been halved: exercises the "too wide" repeat
+    c = tk.Context(0, seed=5).set_param("t_fin", 64).set_param("s_target", 16)
+    c.set_param("r_max", 32)
+    keys = synth.small_alphabet_u32(20000, 5, 4)
+    wide = 0
+    for k in (1, 2, 10000, 20000):
+        recs = run_and_compare(c, keys, k, False, dev)
+        wide += sum(1 for r in recs if not r["ok"] and r["nb"] == r["n_cur"])
+    assert wide > 0
+
+
+def test_tiny_t_fin_cannot_converge_on_both_sides(dev):
+    # a subproblem of 2 elements cannot shrink below t_fin = 1 (every round's
+    # b keeps both): device and oracle both spend the budget and say so
     c = tk.Context(0, seed=5).set_param("t_fin", 1).set_param("s_target", 16)
     keys = synth.small_alphabet_u32(20000, 5, 4)
-    for k in (1, 2, 10000, 20000):
-        run_and_compare(c, keys, k, False, dev)
+    res = c.select(to_dev(keys, dev), 10000)
+    torch.cuda.synchronize()
+    rc, _, _, rrecs = oracle.replay(keys, 10000, False, **replay_params(c, keys.size))
+    assert rc == 1 and int(res["status"].item()) == tk.STATUS_NO_CONVERGENCE
+    assert c.trace_rounds(res) == rrecs[:32]
 
 
 def test_deterministic_repeat(ctx, dev):
