@@ -40,14 +40,14 @@ Layout make_layout(const topk_ctx *c, uint64_t n, uint32_t flags)
     size_t off = 0;
     L.state = off;
     off = align_up(off + sizeof(State));
-    L.ntiles_max = (uint32_t)((n + 3 + SW_TILE - 1) / SW_TILE);
+    L.ntiles_max = (uint32_t)((n + SW_TILE_BAND - 1) / SW_TILE_BAND);
     L.stat = off;
     off = align_up(off + (size_t)4 * L.ntiles_max * sizeof(uint64_t));
     uint64_t cap = n / (uint64_t)c->band_div + 65536;
     if (cap > n) cap = n;
     if (n <= (uint64_t)c->t_fin) cap = 0;
     L.band_cap = (uint32_t)cap;
-    L.band_alloc = (uint32_t)((cap + SW_TILE - 1) / SW_TILE * SW_TILE);
+    L.band_alloc = (uint32_t)((cap + 63) / 64 * 64);
     for (int i = 0; i < 4; ++i) {
         L.band[i] = off;
         off = align_up(off + (size_t)L.band_alloc * sizeof(uint32_t));
@@ -115,7 +115,6 @@ int select_common(topk_ctx *c, const K *keys, uint64_t n, uint64_t k, uint32_t f
     char *w = (char *)ws;
     SelArgs a{};
     a.keys = (const uint32_t *)keys;
-    a.mis = (uint32_t)(((uintptr_t)keys & 15u) >> 2);
     a.n = (uint32_t)n;
     a.k = (uint32_t)k;
     a.flags = flags;
@@ -147,12 +146,12 @@ int select_common(topk_ctx *c, const K *keys, uint64_t n, uint64_t k, uint32_t f
     int r = plan_rounds(c, n, k, sizes, 8);
     if (c->r_fast >= 0) r = (int)c->r_fast;
     P.r_fast = r;
-    const int gmax = c->num_cu * 8;
+    const int gmax = sweep_max_grid(is_f32, (flags & TOPK_LARGEST) != 0, c->num_cu);
     for (int i = 0; i < 8; ++i) {
         // round i's expected input, with slack; rounds beyond the plan get the
         // full grid (they only run after a repeated round)
-        const double ni = (i == 0 || i >= r) ? (double)n : sizes[i] * 1.25 + SW_TILE;
-        const uint64_t t = (uint64_t)ceil(ni / SW_TILE) + 1;
+        const double ni = (i == 0 || i >= r) ? (double)n : sizes[i] * 1.25 + SW_TILE_BAND;
+        const uint64_t t = (uint64_t)ceil(ni / (i == 0 ? SW_TILE_IN : SW_TILE_BAND)) + 1;
         P.sweep_grid[i] = (int)(t < (uint64_t)gmax ? t : (uint64_t)gmax);
     }
     P.clear_blocks = (int)((a.clear_words + PV_THREADS * 8 - 1) / (PV_THREADS * 8));

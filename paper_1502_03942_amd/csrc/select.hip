@@ -56,7 +56,7 @@ __device__ __forceinline__ void hist_add(u32 *h, int d)
 }
 
 template <int M>
-__device__ void radix_select(const u64 (&v)[M], int cnt, const u64 rank_in[2],
+__device__ __forceinline__ void radix_select(const u64 (&v)[M], int cnt, const u64 rank_in[2],
                              const bool act[2], u64 out[2], Smem &sm)
 {
     const u32 tid = threadIdx.x;
@@ -132,7 +132,7 @@ __device__ void radix_select(const u64 (&v)[M], int cnt, const u64 rank_in[2],
 // of Delta = ceil(c sqrt(m_hi (s - m_lo) / s)) + 1 with c = c_num / 4:
 // the least D with 16 s D^2 >= c_num^2 m_hi (s - m_lo).
 // ---------------------------------------------------------------------------
-__device__ void pivot_ranks(u64 s, u64 k, u64 n, u32 c_num, i64 &lo, i64 &hi)
+__device__ __forceinline__ void pivot_ranks(u64 s, u64 k, u64 n, u32 c_num, i64 &lo, i64 &hi)
 {
     if (s == 0) { lo = -1; hi = 0; return; }
     const u64 m_lo = k * s / n;
@@ -150,7 +150,7 @@ __device__ void pivot_ranks(u64 s, u64 k, u64 n, u32 c_num, i64 &lo, i64 &hi)
 // ---------------------------------------------------------------------------
 // State machine pieces (thread 0 of the driving workgroup).
 // ---------------------------------------------------------------------------
-__device__ void state_init(const SelArgs &a, State *st)
+__device__ __forceinline__ void state_init(const SelArgs &a, State *st)
 {
     st->phase = PH_PIVOT;
     st->n_cur = a.n;
@@ -159,7 +159,6 @@ __device__ void state_init(const SelArgs &a, State *st)
     st->src = 0;
     st->tag = 0;
     st->c_num = a.c_num0;
-    st->ticket = 0;
     st->na = st->nb = 0;
     st->nrec = 0;
 }
@@ -169,7 +168,7 @@ __device__ void state_init(const SelArgs &a, State *st)
 // buffer and than the subproblem.  Otherwise repeat the round on the same
 // subproblem with a fresh stream: after a miss (the Algorithm's recursions
 // into a or c) with c doubled, after a too wide b with c halved.
-__device__ void driver_eval(const SelArgs &a, State *st)
+__device__ __forceinline__ void driver_eval(const SelArgs &a, State *st)
 {
     if (st->phase != PH_SWEEP) return;
     const u32 tag = st->tag, na = st->na, nb = st->nb;
@@ -225,7 +224,7 @@ __device__ __forceinline__ u64 fetch_elem(const SelArgs &a, u32 src, u64 p)
 // (draw/4, t, attempt, 0) and key = seed; it keeps at most SEG_CAP positions.
 // ---------------------------------------------------------------------------
 template <bool IS_F32, bool LARGEST>
-__device__ void sample_and_pivot(const SelArgs &a, State *st, Smem &sm)
+__device__ __forceinline__ void sample_and_pivot(const SelArgs &a, State *st, Smem &sm)
 {
     const u32 tid = threadIdx.x;
     const u32 n = sm.n_cur, k = sm.k_cur, src = sm.src, tag = sm.tag;
@@ -314,9 +313,9 @@ __device__ void sample_and_pivot(const SelArgs &a, State *st, Smem &sm)
             R.tag = tag;
             st->nrec = tag + 1;
         }
-        st->ticket = 0;
         st->phase = PH_SWEEP;
     }
+    if (tid < NTICKET) st->tickets[tid] = 0u;
     __syncthreads();
 }
 
@@ -327,7 +326,7 @@ __device__ void sample_and_pivot(const SelArgs &a, State *st, Smem &sm)
 // written in sequence order after the cursor.
 // ---------------------------------------------------------------------------
 template <bool IS_F32, bool LARGEST>
-__device__ void finish(const SelArgs &a, State *st, Smem &sm)
+__device__ __forceinline__ void finish(const SelArgs &a, State *st, Smem &sm)
 {
     const u32 tid = threadIdx.x;
     const u32 n = sm.n_cur, k = sm.k_cur, src = sm.src;
@@ -378,7 +377,7 @@ __device__ void finish(const SelArgs &a, State *st, Smem &sm)
 // done by one workgroup in order, with a running offset instead of look-back.
 // ---------------------------------------------------------------------------
 template <bool IS_F32, bool LARGEST>
-__device__ void block_sweep(const SelArgs &a, State *st, Smem &sm)
+__device__ __forceinline__ void block_sweep(const SelArgs &a, State *st, Smem &sm)
 {
     const u32 tid = threadIdx.x;
     const u32 n = sm.n_cur, src = sm.src;
@@ -506,7 +505,7 @@ __global__ __launch_bounds__(PV_THREADS) void k_tail(SelArgs a)
 // add predecessors' counts 64 tiles at a time until a tile with an inclusive
 // prefix (flag 2) is met, publish this tile's inclusive prefix.  Status word =
 // flag << 32 | value, cleared to 0 before the sweep.
-__device__ void lookback(u64 *sa, u64 *sb, u32 tile, u32 agg_a, u32 agg_b,
+__device__ __forceinline__ void lookback(u64 *sa, u64 *sb, u32 tile, u32 agg_a, u32 agg_b,
                          u32 &ex_a, u32 &ex_b)
 {
     constexpr u64 F_AGG = 1ull << 32, F_INC = 2ull << 32;
@@ -569,158 +568,331 @@ __device__ void lookback(u64 *sa, u64 *sb, u32 tile, u32 agg_a, u32 agg_b,
     ex_b = eb;
 }
 
+// ---------------------------------------------------------------------------
 // The hot loop (§2 Algorithm's partition and reduction; §10 notes that the
-// partition dominates the running time).  A tile is 4 chunks of 1024
-// consecutive elements; in chunk j thread t holds elements 4t..4t+3, loaded
-// with one 128-bit load.  Tiles are taken in order from an atomic ticket, so
-// every tile a look-back waits for belongs to a running workgroup.  FIRST only
-// names the instance enqueued for the first round (which always reads the
-// input) apart from later rounds' instances in profiles.
-template <bool IS_F32, bool LARGEST, bool FIRST>
-__global__ __launch_bounds__(SW_THREADS) void k_sweep(SelArgs a)
+// partition dominates the running time).
+//
+// Geometry.  A workgroup of 16 waves takes one tile; wave w owns 64 * ITEMS
+// consecutive elements of it and element (j, lane) of the wave is
+// wave_base + 64 j + lane, so every load instruction reads 256 contiguous
+// bytes and the stable (sequence-order) position of an element inside its
+// wave is a running count plus one mbcnt.
+//
+// Classification.  Keys are compared with the pivots in their own type: f32
+// keys as floats (with -0 == +0 and NaN above everything expressed through
+// the IEEE predicates), u32 keys and band ords as integers; the position
+// breaks ties only when a key equals a pivot.  A compare result is already
+// the wave's ballot, so |a| and |b| per wave are scalar popcounts.  Pass 1
+// counts and notes which columns j hold any element of a or b; after the
+// tile's offsets are known, pass 2 recomputes those columns and writes.
+//
+// Offsets.  Tiles are taken in order from one atomic ticket (fetched one tile
+// ahead) and their prefix comes from a single-pass decoupled look-back
+// (Merrill & Garland 2016): every tile a look-back waits for is held by a
+// running workgroup, so the sweep completes for any grid size.
+// ---------------------------------------------------------------------------
+struct Piv {
+    u32 lo, li, ro, ri;     // pivot ords and positions (selection order); absent
+                            // pivots are sentinels no (ord, position) pair passes
+    float lv, rv;           // f32 input: pivot values
+    u64 hlm, hrm;           // all ones if the pivot is present, else 0
+    bool fast;              // f32 input: neither pivot is NaN
+};
+
+__device__ __forceinline__ u32 bits_from_ord(u32 o)
 {
-    constexpr int NW = SW_THREADS / WAVE;
-    constexpr int CH = SW_ITEMS / 4;
-    State *st = a.st;
-    if (st->phase != PH_SWEEP) return;
-    const u32 n = st->n_cur, src = st->src, tag = st->tag;
-    const u32 mis = src == 0 ? a.mis : 0u;
-    const u32 ntiles = (u32)(((u64)n + mis + SW_TILE - 1) / SW_TILE);
-    if (blockIdx.x >= ntiles) return;
-    const u64 L64 = st->has_l ? pack(st->l_ord, st->l_idx) : 0ull;
-    const u64 R64 = st->has_r ? pack(st->r_ord, st->r_idx) : ~0ull;
-    const u64 cursor = st->cursor;
-    u64 *sa = a.stat + (u64)(tag & 1u) * 2 * a.ntiles_max;
-    u64 *sb = sa + a.ntiles_max;
-    u64 *nx = a.stat + (u64)((tag + 1u) & 1u) * 2 * a.ntiles_max;
-    const u32 di = (src == 1) ? 1u : 0u;
-    u32 *__restrict__ dord = a.band_ord[di];
-    u32 *__restrict__ didx = a.band_idx[di];
-    const u32 *__restrict__ sord = src ? a.band_ord[src - 1] : nullptr;
-    const u32 *__restrict__ sidx = src ? a.band_idx[src - 1] : nullptr;
-    const u32 *__restrict__ kbase = a.keys - mis;
-    const bool wkeys = (a.flags & TOPK_WRITE_KEYS) && a.out_keys;
-    const u32 tid = threadIdx.x, w = tid / WAVE;
+    return (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
+}
 
-    __shared__ u32 s_tile;
-    __shared__ u32 s_w[CH][NW];
-    __shared__ u32 s_ex[2];
+template <bool IS_F32, bool LARGEST>
+__device__ __forceinline__ Piv load_pivots(const State *st)
+{
+    Piv p;
+    const bool hl = st->has_l != 0, hr = st->has_r != 0;
+    p.hlm = hl ? ~0ull : 0ull;
+    p.hrm = hr ? ~0ull : 0ull;
+    p.lo = hl ? st->l_ord : 0u;
+    p.li = hl ? st->l_idx : 0u;
+    p.ro = hr ? st->r_ord : 0xFFFFFFFFu;
+    p.ri = hr ? st->r_idx : 0xFFFFFFFFu;
+    p.fast = true;
+    p.lv = p.rv = 0.f;
+    if (IS_F32) {
+        const u32 ls = LARGEST ? ~p.lo : p.lo, rs = LARGEST ? ~p.ro : p.ro;
+        p.fast = (!hl || ls != 0xFFFFFFFFu) && (!hr || rs != 0xFFFFFFFFu);
+        p.lv = __uint_as_float(bits_from_ord(ls));
+        p.rv = __uint_as_float(bits_from_ord(rs));
+    }
+    return p;
+}
 
-    for (;;) {
-        if (tid == 0) s_tile = atomicAdd(&st->ticket, 1u);
+// Lane masks of the elements below l (part a) and above r (part c) in one
+// column, branch-free.  KIND 0: x = f32 key bits compared as floats (FAST: no
+// NaN pivot; then -0 == +0 and NaN above all follow from the IEEE predicates),
+// 1: x = u32 key, 2: x = band ord; KIND 0 without FAST compares ords.
+// i = the element's position (it breaks ties with a pivot).
+template <int KIND, bool LARGEST, bool FAST>
+__device__ __forceinline__ void classify(u32 x, u32 i, const Piv &p, u64 &mbelow, u64 &mabove)
+{
+    if (KIND == 0 && FAST) {
+        const float f = __uint_as_float(x);
+        const bool bl = (LARGEST ? !(f <= p.lv) : (f < p.lv)) || (f == p.lv && i < p.li);
+        const bool ab = (LARGEST ? (f < p.rv) : !(f <= p.rv)) || (f == p.rv && i > p.ri);
+        mbelow = ballot(bl) & p.hlm;
+        mabove = ballot(ab) & p.hrm;
+    } else {
+        const u32 o = KIND == 0 ? key_ord<true, LARGEST>(x) : KIND == 1 ? (LARGEST ? ~x : x) : x;
+        mbelow = ballot(o < p.lo || (o == p.lo && i < p.li));
+        mabove = ballot(o > p.ro || (o == p.ro && i > p.ri));
+    }
+}
+
+// LDS ring shared by the control wave and the data waves of a sweep workgroup.
+struct SwSlot {
+    u32 mask[SW_DW][64][4];     // data wave, column: a mask (lo, hi), b mask (lo, hi)
+    u32 stash[SW_DW][SW_STASH]; // ords of the tile's b elements, per data wave, in order
+    u32 cnt[SW_DW];             // per data wave: |a| | |b| << 16
+    u32 off[SW_DW];             // per data wave: offset inside the tile (a | b << 16)
+    u32 ex_a, ex_b;             // the tile's exclusive prefix
+    u32 tile_next;              // tile id handed to the data waves two tiles ahead
+    u32 sig;                    // data waves that have stashed this tile
+};
+struct SwShared {
+    SwSlot slot[2];
+    u32 ready;                  // tiles (in this workgroup's order) whose prefix is known
+};
+
+__device__ __forceinline__ u32 lds_acquire(u32 *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_release(u32 *p, u32 v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// One sweep workgroup.  Wave 0 (control) takes tickets, waits until the data
+// waves have counted a tile, turns the per-wave counts into offsets, runs the
+// look-back and publishes the tile's prefix.  Waves 1..15 (data) each own
+// 64 * COLS consecutive elements of a tile; per tile they classify and count
+// (pass 1), keep the column masks and the b elements' ords in LDS, issue the
+// loads of their next tile, and then write the previous tile (pass 2) once its
+// prefix is known -- so the look-back and the writes overlap the next loads.
+template <int KIND, bool IS_F32, bool LARGEST, bool FAST>
+__device__ __forceinline__ void sweep_pipe(const SelArgs &a, State *st, const Piv &p, u32 n,
+                                           u32 src, u32 tag, SwShared &sh)
+{
+    constexpr int COLS = KIND == 2 ? SW_COLS_BAND : SW_COLS_IN;
+    constexpr u32 WSPAN = (u32)WAVE * COLS;
+    constexpr u32 TILE = (u32)SW_DW * WSPAN;
+    const u32 ntiles = (u32)(((u64)n + TILE - 1) / TILE);
+    const u32 lane = lane_id();
+    const u32 w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+
+    if (w == 0) {
+        // ---------------- control wave ----------------
+        u64 *sa = a.stat + (u64)(tag & 1u) * 2 * a.ntiles_max;
+        u64 *sb = sa + a.ntiles_max;
+        u64 *nx = a.stat + (u64)((tag + 1u) & 1u) * 2 * a.ntiles_max;
+        u32 *ctr = &st->tickets[0];
+        u32 t0 = 0, t1 = 0, pref = 0;
+        if (lane == 0) {
+            t0 = atomicAdd(ctr, 1u);
+            t1 = atomicAdd(ctr, 1u);
+            pref = atomicAdd(ctr, 1u);
+            sh.slot[0].tile_next = t0;
+            sh.slot[1].tile_next = t1;
+            sh.slot[0].sig = 0u;
+            sh.slot[1].sig = 0u;
+            sh.ready = 0u;
+        }
+        u32 cur = __shfl(t0, 0, WAVE), nxt = __shfl(t1, 0, WAVE);
         __syncthreads();
-        const u32 tile = s_tile;
-        if (tile >= ntiles) break;
-        if (tid == 0) {
-            nx[tile] = 0ull;
-            nx[a.ntiles_max + tile] = 0ull;
-        }
-        u32 ord[SW_ITEMS], idx[SW_ITEMS], bits[SW_ITEMS];
-        u32 fa = 0, fb = 0;   // bit (4j+u): element (j,u) is in a / in b
-#pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            const u64 q0 = (u64)tile * SW_TILE + (u64)j * (SW_THREADS * 4) + (u64)tid * 4;
-            if (src == 0) {
-                u32x4 x = {0u, 0u, 0u, 0u};
-                if (q0 < (u64)n + mis)
-                    x = __builtin_nontemporal_load((const u32x4 *)(kbase + q0));
-                bits[4 * j + 0] = x.x; bits[4 * j + 1] = x.y;
-                bits[4 * j + 2] = x.z; bits[4 * j + 3] = x.w;
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    ord[4 * j + u] = key_ord<IS_F32, LARGEST>(bits[4 * j + u]);
-                    idx[4 * j + u] = (u32)(q0 + u - mis);
-                }
-            } else {
-                u32x4 o = {0u, 0u, 0u, 0u}, x = {0u, 0u, 0u, 0u};
-                if (q0 < (u64)n) {
-                    o = __builtin_nontemporal_load((const u32x4 *)(sord + q0));
-                    x = __builtin_nontemporal_load((const u32x4 *)(sidx + q0));
-                }
-                ord[4 * j + 0] = o.x; ord[4 * j + 1] = o.y; ord[4 * j + 2] = o.z; ord[4 * j + 3] = o.w;
-                idx[4 * j + 0] = x.x; idx[4 * j + 1] = x.y; idx[4 * j + 2] = x.z; idx[4 * j + 3] = x.w;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const u64 vp = q0 + u;
-                const bool valid = vp >= mis && vp < (u64)n + mis;
-                const u64 e = pack(ord[4 * j + u], idx[4 * j + u]);
-                const bool below = e < L64;
-                const bool above = e > R64;
-                fa |= (u32)(valid && below) << (4 * j + u);
-                fb |= (u32)(valid && !below && !above) << (4 * j + u);
-            }
-        }
-        // per chunk: wave counts and this lane's prefix within the wave
-        u32 lpa[CH], lpb[CH];
-#pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            u32 ta = 0, tb = 0, pa = 0, pb = 0;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const u64 ba = ballot((fa >> (4 * j + u)) & 1u);
-                const u64 bb = ballot((fb >> (4 * j + u)) & 1u);
-                pa += mbcnt(ba);
-                pb += mbcnt(bb);
-                ta += (u32)__popcll(ba);
-                tb += (u32)__popcll(bb);
-            }
-            lpa[j] = pa;
-            lpb[j] = pb;
-            if (lane_id() == 0) s_w[j][w] = ta | (tb << 16);
-        }
-        __syncthreads();
-        u32 basep[CH], tot = 0;
-#pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            u32 bw = 0, cj = 0;
-#pragma unroll
-            for (int x = 0; x < NW; ++x) {
-                const u32 c = s_w[j][x];
-                bw += (x < (int)w) ? c : 0u;
-                cj += c;
-            }
-            basep[j] = tot + bw;
-            tot += cj;
-        }
-        if (w == 0) {
+        for (u32 i = 0; cur < ntiles; ++i) {
+            SwSlot &S = sh.slot[i & 1u];
+            while (lds_acquire(&S.sig) < (u32)SW_DW) __builtin_amdgcn_s_sleep(1);
+            const u32 c = lane < (u32)SW_DW ? S.cnt[lane] : 0u;
+            const u32 inc = wave_incl_scan(c);
+            if (lane < (u32)SW_DW) S.off[lane] = inc - c;
+            const u32 tot = __shfl(inc, SW_DW - 1, WAVE);
             u32 ea, eb;
-            lookback(sa, sb, tile, tot & 0xFFFFu, tot >> 16, ea, eb);
-            if (lane_id() == 0) {
-                s_ex[0] = ea;
-                s_ex[1] = eb;
-                if (tile == ntiles - 1) {
+            lookback(sa, sb, cur, tot & 0xFFFFu, tot >> 16, ea, eb);
+            const u32 after = __shfl(pref, 0, WAVE);   // tile id two ahead
+            if (lane == 0) {
+                S.ex_a = ea;
+                S.ex_b = eb;
+                if (cur == ntiles - 1) {
                     st->na = ea + (tot & 0xFFFFu);
                     st->nb = eb + (tot >> 16);
                 }
+                nx[cur] = 0ull;                     // the next sweep's status words
+                nx[a.ntiles_max + cur] = 0ull;
+                S.sig = 0u;
+                S.tile_next = after;
+                lds_release(&sh.ready, i + 1);
+                pref = atomicAdd(ctr, 1u);
             }
+            cur = nxt;
+            nxt = after;
         }
-        __syncthreads();
-        const u64 ex_a = s_ex[0], ex_b = s_ex[1];
-#pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            u64 pa = cursor + ex_a + (basep[j] & 0xFFFFu) + lpa[j];
-            u64 pb = ex_b + (basep[j] >> 16) + lpb[j];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int i = 4 * j + u;
-                if ((fa >> i) & 1u) {
-                    if (pa < a.k) {
-                        a.out_idx[pa] = idx[i];
-                        if (wkeys) a.out_keys[pa] = src == 0 ? bits[i] : a.keys[idx[i]];
-                    }
-                    ++pa;
-                }
-                if ((fb >> i) & 1u) {
-                    if (pb < a.band_cap) {
-                        dord[pb] = ord[i];
-                        didx[pb] = idx[i];
-                    }
-                    ++pb;
-                }
-            }
-        }
+        return;
     }
+
+    // ---------------- data waves ----------------
+    const u32 dw = w - 1;
+    const u64 cursor = st->cursor;
+    const u32 di = (src == 1) ? 1u : 0u;
+    u32 *__restrict__ dord = a.band_ord[di];
+    u32 *__restrict__ didx = a.band_idx[di];
+    const u32 *__restrict__ sord = KIND == 2 ? a.band_ord[src - 1] : a.keys;
+    const u32 *__restrict__ sidx = KIND == 2 ? a.band_idx[src - 1] : a.keys;
+    const bool wkeys = (a.flags & TOPK_WRITE_KEYS) && a.out_keys;
+    __syncthreads();
+    u32 cur = __builtin_amdgcn_readfirstlane(sh.slot[0].tile_next);
+    u32 x[COLS], ix[COLS];
+
+    // loads of this wave's part of `tile` (elements past n read as 0, never classified)
+    auto issue = [&](u32 tile) {
+        const u64 wb = (u64)tile * TILE + (u64)dw * WSPAN;
+        const int rem = wb >= (u64)n ? 0 : (int)((u64)n - wb < WSPAN ? (u64)n - wb : WSPAN);
+        const u32 *__restrict__ pw = sord + wb;
+        const u32 *__restrict__ pi = sidx + wb;
+        u32 ln = lane;
+        asm volatile("" : "+v"(ln));
+#pragma unroll
+        for (int j = 0; j < COLS; ++j) {
+            const bool ok = (int)ln < rem - j * WAVE;
+            x[j] = ok ? __builtin_nontemporal_load(pw + j * WAVE + ln) : 0u;
+            if (KIND == 2) ix[j] = ok ? __builtin_nontemporal_load(pi + j * WAVE + ln) : 0u;
+        }
+    };
+    if (cur < ntiles) issue(cur);
+
+    bool have_prev = false;
+    u32 prev = 0;
+    for (u32 i = 0;; ++i) {
+        SwSlot &S = sh.slot[i & 1u];
+        if (cur < ntiles) {
+            // pass 1: classify, count, keep masks (lane j holds column j) and b ords
+            const u64 wb = (u64)cur * TILE + (u64)dw * WSPAN;
+            const int rem = wb >= (u64)n ? 0 : (int)((u64)n - wb < WSPAN ? (u64)n - wb : WSPAN);
+            const u32 ib = (u32)wb;
+            u32 ln = lane;
+            asm volatile("" : "+v"(ln));
+            u32 m0 = 0, m1 = 0, m2 = 0, m3 = 0, ta = 0, tb = 0;
+#pragma unroll
+            for (int j = 0; j < COLS; ++j) {
+                const u32 ie = KIND == 2 ? ix[j] : ib + (u32)(j * WAVE) + ln;
+                u64 mbl, mab;
+                classify<KIND, LARGEST, FAST>(x[j], ie, p, mbl, mab);
+                const u64 mv = ballot((int)ln < rem - j * WAVE);
+                const u64 ma = mbl & mv, mb = ~mbl & ~mab & mv;
+                if (ln == (u32)j) {
+                    m0 = (u32)ma; m1 = (u32)(ma >> 32);
+                    m2 = (u32)mb; m3 = (u32)(mb >> 32);
+                }
+                if (KIND != 2 && mb) {
+                    if ((mb >> ln) & 1ull) {
+                        const u32 q = tb + mbcnt(mb);
+                        if (q < (u32)SW_STASH)
+                            S.stash[dw][q] = KIND == 0 ? key_ord<true, LARGEST>(x[j]) : (LARGEST ? ~x[j] : x[j]);
+                    }
+                }
+                ta += (u32)__popcll(ma);
+                tb += (u32)__popcll(mb);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            *(uint4 *)&S.mask[dw][ln][0] = make_uint4(m0, m1, m2, m3);
+            if (lane == 0) {
+                S.cnt[dw] = ta | (tb << 16);
+                __hip_atomic_fetch_add(&S.sig, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+        if (have_prev)
+            while (lds_acquire(&sh.ready) < i) __builtin_amdgcn_s_sleep(1);
+        u32 nxt = ntiles;
+        if (cur < ntiles) nxt = __builtin_amdgcn_readfirstlane(sh.slot[(i + 1) & 1u].tile_next);
+        if (nxt < ntiles) issue(nxt);
+        if (have_prev) {
+            // pass 2 of the previous tile: write a's positions and b's pairs
+            SwSlot &P = sh.slot[(i - 1) & 1u];
+            const u64 wb = (u64)prev * TILE + (u64)dw * WSPAN;
+            const u32 offp = P.off[dw];
+            const u32 cb = P.cnt[dw] >> 16;
+            u64 pa = cursor + P.ex_a + (offp & 0xFFFFu);
+            u64 pb = (u64)P.ex_b + (offp >> 16);
+            u32 ln = lane;
+            asm volatile("" : "+v"(ln));
+            const uint4 mm = *(const uint4 *)&P.mask[dw][ln][0];
+            u32 sbr = 0;
+            const bool stashed = KIND != 2 && cb <= (u32)SW_STASH;
+            const u32 *__restrict__ pw = sord + wb;
+            const u32 *__restrict__ pi = sidx + wb;
+#pragma unroll
+            for (int j = 0; j < COLS; ++j) {
+                const u64 ma = ((u64)(u32)__builtin_amdgcn_readlane(mm.y, j) << 32) |
+                               (u32)__builtin_amdgcn_readlane(mm.x, j);
+                const u64 mb = ((u64)(u32)__builtin_amdgcn_readlane(mm.w, j) << 32) |
+                               (u32)__builtin_amdgcn_readlane(mm.z, j);
+                if (ma | mb) {
+                    const bool ia = (ma >> ln) & 1ull, ibm = (mb >> ln) & 1ull;
+                    // values not kept in LDS are read again (these columns were just loaded)
+                    const bool need = (KIND == 2 && (ia || ibm)) || (ibm && !stashed) || (ia && wkeys);
+                    u32 xv = 0, iv = 0;
+                    if (need) {
+                        xv = pw[j * WAVE + ln];
+                        if (KIND == 2) iv = pi[j * WAVE + ln];
+                    }
+                    const u32 ie = KIND == 2 ? iv : (u32)wb + (u32)(j * WAVE) + ln;
+                    if (ia) {
+                        const u64 q = pa + mbcnt(ma);
+                        if (q < a.k) {
+                            a.out_idx[q] = ie;
+                            if (wkeys) a.out_keys[q] = KIND == 2 ? a.keys[ie] : xv;
+                        }
+                    }
+                    if (ibm) {
+                        const u32 r = mbcnt(mb);
+                        const u64 q = pb + r;
+                        if (q < a.band_cap) {
+                            dord[q] = stashed ? P.stash[dw][sbr + r]
+                                    : KIND == 0 ? key_ord<true, LARGEST>(xv)
+                                    : KIND == 1 ? (LARGEST ? ~xv : xv) : xv;
+                            didx[q] = ie;
+                        }
+                    }
+                    pa += (u64)__popcll(ma);
+                    pb += (u64)__popcll(mb);
+                    sbr += (u32)__popcll(mb);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        if (cur >= ntiles) break;
+        have_prev = true;
+        prev = cur;
+        cur = nxt;
+    }
+}
+
+// FIRST only names the instance enqueued for the first round (which reads
+// the input) apart from later rounds' instances in profiles.
+template <bool IS_F32, bool LARGEST, bool FIRST>
+__global__ __launch_bounds__(SW_THREADS) void k_sweep(SelArgs a)
+{
+    State *st = a.st;
+    if (st->phase != PH_SWEEP) return;
+    const u32 n = st->n_cur, src = st->src, tag = st->tag;
+    __shared__ SwShared sh;
+    const Piv p = load_pivots<IS_F32, LARGEST>(st);
+    if (src != 0)
+        sweep_pipe<2, IS_F32, LARGEST, true>(a, st, p, n, src, tag, sh);
+    else if (!IS_F32)
+        sweep_pipe<1, IS_F32, LARGEST, true>(a, st, p, n, src, tag, sh);
+    else if (p.fast)
+        sweep_pipe<0, IS_F32, LARGEST, true>(a, st, p, n, src, tag, sh);
+    else
+        sweep_pipe<0, IS_F32, LARGEST, false>(a, st, p, n, src, tag, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -773,6 +945,21 @@ static hipError_t launch_impl(SelArgs a, const SelLaunch &L, hipStream_t s, Kern
     hipLaunchKernelGGL((k_tail<F, LG>), dim3(1), dim3(PV_THREADS), 0, s, a);
     tm_end(tm, t, s);
     return hipGetLastError();
+}
+
+// Workgroups of k_sweep that fit on the device at once.
+int sweep_max_grid(bool is_f32, bool largest, int num_cu)
+{
+    int nb = 0;
+    hipError_t e;
+    if (is_f32)
+        e = largest ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep<true, true, true>, SW_THREADS, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep<true, false, true>, SW_THREADS, 0);
+    else
+        e = largest ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep<false, true, true>, SW_THREADS, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep<false, false, true>, SW_THREADS, 0);
+    if (e != hipSuccess || nb < 1) nb = 1;
+    return nb * num_cu;
 }
 
 hipError_t launch_select(const SelArgs &a, const SelLaunch &L, hipStream_t stream,

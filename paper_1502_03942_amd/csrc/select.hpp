@@ -10,10 +10,15 @@ constexpr int SEG_CAP = 16;                    // samples kept per sampler segme
 constexpr int NSEG = PV_THREADS;               // sampler segments (one per thread)
 constexpr int FIN_ITEMS = 16;                  // finisher keys per thread
 constexpr int T_FIN_MAX = PV_THREADS * FIN_ITEMS;
-constexpr int SW_THREADS = 256;                // multi-workgroup sweep
-constexpr int SW_ITEMS = 16;                   // keys per thread per tile
-constexpr int SW_TILE = SW_THREADS * SW_ITEMS; // 4096 keys per tile
+constexpr int SW_THREADS = 1024;               // multi-workgroup sweep: 1 control + 15 data waves
+constexpr int SW_DW = SW_THREADS / 64 - 1;     // data waves
+constexpr int SW_COLS_IN = 64;                 // input keys per data-wave lane per tile
+constexpr int SW_COLS_BAND = 32;               // band pairs per data-wave lane per tile
+constexpr int SW_TILE_IN = SW_DW * 64 * SW_COLS_IN;     // 61440 keys
+constexpr int SW_TILE_BAND = SW_DW * 64 * SW_COLS_BAND; // 30720 pairs
+constexpr int SW_STASH = 512;                  // band ords kept in LDS per data wave and tile
 constexpr int R_TRACE = 32;                    // attempt records kept
+constexpr int NTICKET = 64;                    // ticket words kept zeroed for the sweep
 constexpr int TRACE_STRIDE = NSEG * SEG_CAP;   // sample positions per record
 
 enum : uint32_t { PH_PIVOT = 0, PH_SWEEP = 1, PH_DONE = 2, PH_ERROR = 3 };
@@ -27,16 +32,16 @@ struct RoundRec {                 // same layout as topk_round_record
 
 struct State {
     uint32_t phase, n_cur, k_cur, cursor;
-    uint32_t src, tag, c_num, ticket;
+    uint32_t src, tag, c_num, pad3;
     uint32_t na, nb, nrec, pad0;
     uint32_t l_ord, l_idx, r_ord, r_idx;
     uint32_t has_l, has_r, pad1, pad2;
     RoundRec rec[R_TRACE];
+    uint32_t tickets[NTICKET];  // tickets[0]: the sweep's tile counter
 };
 
 struct SelArgs {
     const uint32_t *keys;       // input key bits
-    uint32_t mis;               // keys - 16-byte-aligned base, in elements (0..3)
     uint32_t n, k, flags;
     uint32_t *out_idx, *out_keys, *kth_key, *kth_idx, *status;
     State *st;
@@ -69,5 +74,6 @@ struct KernelTimer {
 
 hipError_t launch_select(const SelArgs &a, const SelLaunch &L, hipStream_t stream,
                          KernelTimer *tm);
+int sweep_max_grid(bool is_f32, bool largest, int num_cu);
 
 }  // namespace topk
