@@ -43,6 +43,7 @@ class Params(ctypes.Structure):
         ("nseg", ctypes.c_uint32), ("seg_cap", ctypes.c_uint32),
         ("t_fin", ctypes.c_uint32), ("r_max", ctypes.c_uint32),
         ("band_cap", ctypes.c_uint64), ("seed", ctypes.c_uint64),
+        ("s_max", ctypes.c_uint32), ("pad", ctypes.c_uint32),
     ]
 
 
@@ -67,6 +68,9 @@ def lib():
         L.orc_pivot_ranks.restype = None
         L.orc_replay.argtypes = [vp, i32, u64, u64, i32, ctypes.POINTER(Params), vp, vp,
                                  ctypes.POINTER(Round), vp]
+        L.orc_hash_taken.argtypes = [u64, u32, u32, u64]
+        L.orc_band_threshold.argtypes = [u64, u64, ctypes.c_int64, ctypes.c_int64, u64]
+        L.orc_band_threshold.restype = u64
         _lib = L
     return _lib
 
@@ -159,15 +163,25 @@ def pivot_ranks(s, k, n, c_num):
     return lo.value, hi.value
 
 
+def hash_taken(seed, tag, x, T):
+    """Per-element Bernoulli decision of the sample drawn while b is formed (§2)."""
+    return bool(lib().orc_hash_taken(seed, tag, x, T))
+
+
+def band_threshold(n_cur, s, lo, hi, s_target):
+    """Rate (as T = rho 2^32) of the sample of the middle part b."""
+    return int(lib().orc_band_threshold(n_cur, s, lo, hi, s_target))
+
+
 def replay(keys, k, largest=False, *, s_target, c_num, nseg, seg_cap, t_fin, r_max,
-           band_cap, seed):
+           band_cap, seed, s_max=16384):
     """Step-by-step replay of the sampling selection (§2 Algorithm, §4.1).
 
     Returns (status, out_idx[k] in the order the recursion writes them,
     kth_idx, list of per-round dicts).
     """
     keys, f = _keys(keys)
-    prm = Params(s_target, c_num, nseg, seg_cap, t_fin, r_max, band_cap, seed)
+    prm = Params(s_target, c_num, nseg, seg_cap, t_fin, r_max, band_cap, seed, s_max, 0)
     out = np.zeros(k, np.uint32)
     kth = np.zeros(1, np.uint32)
     recs = (Round * max(r_max, 1))()

@@ -284,6 +284,39 @@ void orc_pivot_ranks(uint64_t s, uint64_t k, uint64_t n, uint32_t c_num,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Bernoulli sample by per-element decisions (§2, "Bernoulli sampling": every
+ * object is taken independently with probability rho).  Used for the sample of
+ * a subproblem that is being produced element by element: object x (input
+ * position) is taken iff word 0 of Philox4x32-10 at counter (x, 0, tag, 1)
+ * with key = seed is below T = floor(rho 2^32) (T >= 2^32: every object). */
+int orc_hash_taken(uint64_t seed, uint32_t tag, uint32_t x, uint64_t T)
+{
+    uint32_t ctr[4] = {x, 0, tag, 1};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    orc_philox4x32_10(ctr, key, out);
+    return (uint64_t)out[0] < T;
+}
+
+/* Rate of that sample for the middle part b of a round: the pivots cover the
+ * sample ranks [bot, top) with bot = lo (0 without a lower pivot) and
+ * top = hi + 1 (s without an upper pivot), so b is expected to hold about
+ * n_cur (top - bot) / s elements; rho = s_target / that, as T = rho 2^32. */
+uint64_t orc_band_threshold(uint64_t n_cur, uint64_t s, int64_t lo, int64_t hi,
+                            uint64_t s_target)
+{
+    uint64_t nb_est = n_cur;
+    if (s > 0) {
+        int64_t bot = lo >= 0 ? lo : 0;
+        int64_t top = hi < (int64_t)s ? hi + 1 : (int64_t)s;
+        nb_est = n_cur * (uint64_t)(top - bot) / s;
+    }
+    if (nb_est == 0) nb_est = 1;
+    uint64_t T = (s_target << 32) / nb_est;
+    return T;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Replay of the recursive selection (§2, Algorithm "communication efficient
  * selection", with the sampling of §4.1), step by step, on one address space.
  *
@@ -302,8 +335,14 @@ void orc_pivot_ranks(uint64_t s, uint64_t k, uint64_t n, uint32_t c_num,
  * directly: tau = its element of rank k_cur; every element <= tau (in sequence
  * order) is written after the cursor.  More than r_max rounds: status 1.
  *
- * The random stream of attempt number `tag` (0, 1, 2, ... over all attempts)
- * is (seed, tag, segment).  Each round is recorded in recs[]. */
+ * Samples.  The first attempt on the input, and every repeated attempt, uses
+ * the skip sampler over the current sequence with stream (seed, tag,
+ * segment).  After a recursion into b, the next attempt's sample is drawn
+ * while b is formed: each element of b is taken by the per-element rule
+ * (orc_hash_taken) with stream tag + 1 and the rate of orc_band_threshold; if
+ * that sample exceeds s_max elements it is discarded and the skip sampler is
+ * used instead.  The sample is a set: the pivots depend only on its members.
+ * Each round is recorded in recs[]. */
 typedef struct {
     uint32_t n_cur, k_cur;       /* subproblem before the round               */
     uint32_t s;                  /* sample size                                */
@@ -319,11 +358,13 @@ typedef struct {
 typedef struct {
     uint32_t s_target;           /* expected sample size                       */
     uint32_t c_num;              /* initial spread factor numerator (c = /4)   */
-    uint32_t nseg, seg_cap;      /* sampler segmentation                       */
+    uint32_t nseg, seg_cap;      /* skip sampler segmentation                  */
     uint32_t t_fin;              /* solve directly at or below this size       */
     uint32_t r_max;              /* attempt budget                             */
     uint64_t band_cap;           /* capacity for b                             */
     uint64_t seed;
+    uint32_t s_max;              /* largest usable sample                      */
+    uint32_t pad;
 } orc_params;
 
 int orc_replay(const void *keys, int is_f32, uint64_t n, uint64_t k, int largest,
@@ -341,7 +382,10 @@ int orc_replay(const void *keys, int is_f32, uint64_t n, uint64_t k, int largest
     for (uint64_t i = 0; i < n; ++i) cur[i] = (uint32_t)i;
     uint64_t n_cur = n, k_cur = k, cursor = 0;
     uint32_t c_num = prm->c_num, tag = 0, nr = 0;
+    uint32_t *hsamp = (uint32_t *)malloc(((uint64_t)prm->s_max + 1) * sizeof(uint32_t));
+    int64_t hcount = -1;         /* size of the per-element sample of cur; -1: none */
     int status = 0;
+    if (!hsamp) return -2;
     for (;;) {
         if (n_cur <= prm->t_fin) {
             /* base case: sort the small subproblem, tau = rank k_cur */
@@ -357,17 +401,25 @@ int orc_replay(const void *keys, int is_f32, uint64_t n, uint64_t k, int largest
             break;
         }
         if (tag >= prm->r_max) { status = 1; break; }
-        double rho = (double)prm->s_target / (double)n_cur;
-        int64_t s = orc_bernoulli_sample(n_cur, rho, prm->seed, tag, prm->nseg,
-                                         prm->seg_cap, spos, smax);
-        if (s < 0) { status = -4; break; }
-        for (int64_t i = 0; i < s; ++i) samp[i] = cur[spos[i]];
+        int64_t s;
+        if (hcount >= 0) {
+            s = hcount;
+            for (int64_t i = 0; i < s; ++i) samp[i] = hsamp[i];
+        } else {
+            double rho = (double)prm->s_target / (double)n_cur;
+            s = orc_bernoulli_sample(n_cur, rho, prm->seed, tag, prm->nseg,
+                                     prm->seg_cap, spos, smax);
+            if (s < 0) { status = -4; break; }
+            for (int64_t i = 0; i < s; ++i) samp[i] = cur[spos[i]];
+        }
+        hcount = -1;
         qsort_r(samp, (size_t)s, sizeof(uint32_t), cmp_idx, &o);
         int64_t lo, hi;
         orc_pivot_ranks((uint64_t)s, k_cur, n_cur, c_num, &lo, &hi);
         int has_l = lo >= 0, has_r = hi < s;
         uint32_t l = has_l ? samp[lo] : 0, r = has_r ? samp[hi] : 0;
-        uint64_t na = 0, nb = 0;
+        uint64_t na = 0, nb = 0, hs = 0;
+        uint64_t T = orc_band_threshold(n_cur, (uint64_t)s, lo, hi, prm->s_target);
         for (uint64_t i = 0; i < n_cur; ++i) {
             uint32_t e = cur[i];
             if (has_l && precedes(&o, e, l)) {
@@ -378,6 +430,10 @@ int orc_replay(const void *keys, int is_f32, uint64_t n, uint64_t k, int largest
             } else {
                 if (nb < prm->band_cap) nxt[nb] = e;
                 ++nb;
+                if (orc_hash_taken(prm->seed, tag + 1, e, T)) {
+                    if (hs < prm->s_max) hsamp[hs] = e;
+                    ++hs;
+                }
             }
         }
         int miss = na >= k_cur || na + nb < k_cur;
@@ -405,8 +461,9 @@ int orc_replay(const void *keys, int is_f32, uint64_t n, uint64_t k, int largest
         n_cur = nb;
         uint32_t *t = cur; cur = nxt; nxt = t;
         c_num = prm->c_num;
+        hcount = hs <= prm->s_max ? (int64_t)hs : -1;
     }
     if (nrecs) *nrecs = nr;
-    free(cur); free(nxt); free(spos); free(samp);
+    free(cur); free(nxt); free(spos); free(samp); free(hsamp);
     return status;
 }

@@ -30,8 +30,8 @@ constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t x, size_t a = ALIGN) { return (x + a - 1) / a * a; }
 
 struct Layout {
-    size_t state, stat, band[4], trace, total;
-    uint32_t ntiles_max, band_cap, band_alloc;
+    size_t state, hs, band[4], trace, total;
+    uint32_t band_cap, band_alloc;
 };
 
 Layout make_layout(const topk_ctx *c, uint64_t n, uint32_t flags)
@@ -40,9 +40,8 @@ Layout make_layout(const topk_ctx *c, uint64_t n, uint32_t flags)
     size_t off = 0;
     L.state = off;
     off = align_up(off + sizeof(State));
-    L.ntiles_max = (uint32_t)((n + SW_TILE_BAND - 1) / SW_TILE_BAND);
-    L.stat = off;
-    off = align_up(off + (size_t)4 * L.ntiles_max * sizeof(uint64_t));
+    L.hs = off;
+    off = align_up(off + (size_t)S_MAX * sizeof(uint64_t));
     uint64_t cap = n / (uint64_t)c->band_div + 65536;
     if (cap > n) cap = n;
     if (n <= (uint64_t)c->t_fin) cap = 0;
@@ -124,8 +123,7 @@ int select_common(topk_ctx *c, const K *keys, uint64_t n, uint64_t k, uint32_t f
     a.kth_idx = kth_idx;
     a.status = status;
     a.st = (State *)(w + L.state);
-    a.stat = (uint64_t *)(w + L.stat);
-    a.ntiles_max = L.ntiles_max;
+    a.hs_buf = (uint64_t *)(w + L.hs);
     a.band_cap = L.band_cap;
     a.band_ord[0] = (uint32_t *)(w + L.band[0]);
     a.band_idx[0] = (uint32_t *)(w + L.band[1]);
@@ -137,7 +135,6 @@ int select_common(topk_ctx *c, const K *keys, uint64_t n, uint64_t k, uint32_t f
     a.t_fin = (uint32_t)c->t_fin;
     a.r_max = (uint32_t)c->r_max;
     a.seed = c->seed;
-    a.clear_words = 2 * L.ntiles_max;
 
     SelLaunch P{};
     P.is_f32 = is_f32;
@@ -154,7 +151,6 @@ int select_common(topk_ctx *c, const K *keys, uint64_t n, uint64_t k, uint32_t f
         const uint64_t t = (uint64_t)ceil(ni / (i == 0 ? SW_TILE_IN : SW_TILE_BAND)) + 1;
         P.sweep_grid[i] = (int)(t < (uint64_t)gmax ? t : (uint64_t)gmax);
     }
-    P.clear_blocks = (int)((a.clear_words + PV_THREADS * 8 - 1) / (PV_THREADS * 8));
     if (hipSetDevice(c->device) != hipSuccess) return TOPK_E_HIP;
     KernelTimer tm{};
     if (c->timing > 0) {

@@ -33,7 +33,8 @@ struct Smem {
     u64 found[2];
     u64 L64, R64;
     i64 lo, hi;
-    u32 phase, n_cur, k_cur, src, tag, c_num, cursor, s_total;
+    u64 hs_T;
+    u32 phase, n_cur, k_cur, src, tag, c_num, cursor, s_total, hs_ok, hs_count;
 };
 
 // ---------------------------------------------------------------------------
@@ -148,6 +149,49 @@ __device__ __forceinline__ void pivot_ranks(u64 s, u64 k, u64 n, u32 c_num, i64 
 }
 
 // ---------------------------------------------------------------------------
+// Sample drawn while a round's middle part b is formed (§2, "Bernoulli
+// sampling": each object independently with probability rho).  Element x
+// (input position) is taken iff word 0 of Philox4x32-10 at counter
+// (x, 0, tag, 1), key = seed, is below T = rho 2^32.  rho = s_target over the
+// expected |b|: the pivots cover sample ranks [bot, top) with bot = lo (0 if
+// no lower pivot) and top = hi + 1 (s if no upper pivot), so |b| ~ n (top-bot)/s.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ u64 band_threshold(u64 n_cur, u64 s, i64 lo, i64 hi, u64 s_target)
+{
+    u64 nb_est = n_cur;
+    if (s > 0) {
+        const i64 bot = lo >= 0 ? lo : 0;
+        const i64 top = hi < (i64)s ? hi + 1 : (i64)s;
+        nb_est = n_cur * (u64)(top - bot) / s;
+    }
+    if (nb_est == 0) nb_est = 1;
+    return (s_target << 32) / nb_est;
+}
+
+__device__ __forceinline__ bool hash_taken(u64 seed, u32 tag, u32 x, u64 T)
+{
+    const uint4 r = philox4x32_10(make_uint4(x, 0u, tag, 1u), (u32)seed, (u32)(seed >> 32));
+    return (u64)r.x < T;
+}
+
+// Append the taken elements of this wave (lane flag `take`, pair `e`) to the
+// collected sample; positions beyond S_MAX are counted but not stored.
+__device__ __forceinline__ void sample_append(const SelArgs &a, State *st, bool take, u64 e)
+{
+    const u64 m = ballot(take);
+    if (m) {
+        const int first = __ffsll((unsigned long long)m) - 1;
+        u32 base = 0;
+        if ((int)lane_id() == first) base = atomicAdd(&st->hs_count, (u32)__popcll(m));
+        base = __shfl(base, first, WAVE);
+        if (take) {
+            const u32 q = base + mbcnt(m);
+            if (q < (u32)S_MAX) a.hs_buf[q] = e;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // State machine pieces (thread 0 of the driving workgroup).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void state_init(const SelArgs &a, State *st)
@@ -161,6 +205,9 @@ __device__ __forceinline__ void state_init(const SelArgs &a, State *st)
     st->c_num = a.c_num0;
     st->na = st->nb = 0;
     st->nrec = 0;
+    st->hs_ok = 0;
+    st->resv = 0;
+    st->hs_count = 0;
 }
 
 // Branch of the Algorithm after a sweep: recurse into b when the pivots
@@ -171,8 +218,11 @@ __device__ __forceinline__ void state_init(const SelArgs &a, State *st)
 __device__ __forceinline__ void driver_eval(const SelArgs &a, State *st)
 {
     if (st->phase != PH_SWEEP) return;
-    const u32 tag = st->tag, na = st->na, nb = st->nb;
+    const u32 tag = st->tag;
+    const u32 na = (u32)(st->resv >> 32), nb = (u32)st->resv;
     const u32 n = st->n_cur, k = st->k_cur;
+    st->na = na;
+    st->nb = nb;
     const bool miss = na >= k || (u64)na + nb < k;
     const bool wide = nb > a.band_cap || nb == n;
     const bool ok = !miss && !wide;
@@ -182,6 +232,7 @@ __device__ __forceinline__ void driver_eval(const SelArgs &a, State *st)
         st->rec[tag].ok = ok ? 1u : 0u;
     }
     st->tag = tag + 1;
+    st->hs_ok = (ok && st->hs_count <= (u32)S_MAX) ? 1u : 0u;
     if (ok) {
         st->cursor += na;
         st->k_cur = k - na;
@@ -206,6 +257,8 @@ __device__ __forceinline__ void load_state(const State *st, Smem &sm)
     sm.tag = st->tag;
     sm.c_num = st->c_num;
     sm.cursor = st->cursor;
+    sm.hs_ok = st->hs_ok;
+    sm.hs_count = st->hs_count;
 }
 
 // element `p` of the current subproblem as an (ord, position) pair
@@ -232,9 +285,15 @@ __device__ __forceinline__ void sample_and_pivot(const SelArgs &a, State *st, Sm
     const u64 L = ((u64)n + NSEG - 1) / NSEG;
     const u64 s0 = (u64)tid * L;
     const u64 e0 = s0 + L < (u64)n ? s0 + L : (u64)n;
+    const bool collected = sm.hs_ok != 0;   // sample drawn while this subproblem was formed
     u32 pos[SEG_CAP];
     int cnt = 0;
-    if (s0 < e0) {
+    if (collected) {
+        const u32 hc = sm.hs_count;
+#pragma unroll
+        for (int j = 0; j < SEG_CAP; ++j)
+            if (tid + (u32)j * PV_THREADS < hc) cnt = j + 1;
+    } else if (s0 < e0) {
         if (rho >= 1.0) {
 #pragma unroll
             for (int j = 0; j < SEG_CAP; ++j)
@@ -268,11 +327,13 @@ __device__ __forceinline__ void sample_and_pivot(const SelArgs &a, State *st, Sm
     u64 v[SEG_CAP];
 #pragma unroll
     for (int j = 0; j < SEG_CAP; ++j)
-        v[j] = j < cnt ? fetch_elem<IS_F32, LARGEST>(a, src, pos[j]) : ~0ull;
+        v[j] = j >= cnt ? ~0ull
+             : collected ? a.hs_buf[tid + (u32)j * PV_THREADS]
+             : fetch_elem<IS_F32, LARGEST>(a, src, pos[j]);
 
     u32 s_total;
     const u32 excl = block_excl_scan<PV_THREADS>((u32)cnt, sm.scan, &s_total);
-    if (a.trace_pos && tag < R_TRACE) {
+    if (!collected && a.trace_pos && tag < R_TRACE) {
         u32 *tp = a.trace_pos + (u64)tag * TRACE_STRIDE + excl;
 #pragma unroll
         for (int j = 0; j < SEG_CAP; ++j)
@@ -314,8 +375,12 @@ __device__ __forceinline__ void sample_and_pivot(const SelArgs &a, State *st, Sm
             st->nrec = tag + 1;
         }
         st->phase = PH_SWEEP;
+        // the coming sweep reserves output space and draws the next sample
+        st->resv = 0ull;
+        st->hs_count = 0u;
+        st->hs_T = band_threshold(n, s_total, lo, hi, a.s_target);
+        sm.hs_T = st->hs_T;
     }
-    if (tid < NTICKET) st->tickets[tid] = 0u;
     __syncthreads();
 }
 
@@ -422,14 +487,12 @@ __device__ __forceinline__ void block_sweep(const SelArgs &a, State *st, Smem &s
                 }
                 ++pb;
             }
+            sample_append(a, st, fb[u] && hash_taken(a.seed, sm.tag + 1, idx, sm.hs_T), e[u]);
         }
         run_a += tot & 0xFFFFu;
         run_b += tot >> 16;
     }
-    if (tid == 0) {
-        st->na = (u32)run_a;
-        st->nb = (u32)run_b;
-    }
+    if (tid == 0) st->resv = (run_a << 32) | run_b;
     __syncthreads();
 }
 
@@ -439,14 +502,6 @@ __device__ __forceinline__ void block_sweep(const SelArgs &a, State *st, Smem &s
 template <bool IS_F32, bool LARGEST>
 __global__ __launch_bounds__(PV_THREADS) void k_pivot(SelArgs a)
 {
-    if (blockIdx.x > 0) {
-        // first kernel of a call: clear the parity-0 look-back status words
-        const u64 per = (u64)PV_THREADS * 8;
-        const u64 i0 = (u64)(blockIdx.x - 1) * per;
-        for (u64 i = i0 + threadIdx.x; i < i0 + per && i < a.clear_words; i += PV_THREADS)
-            a.stat[i] = 0ull;
-        return;
-    }
     __shared__ Smem sm;
     State *st = a.st;
     if (threadIdx.x == 0) {
@@ -499,73 +554,6 @@ __global__ __launch_bounds__(PV_THREADS) void k_tail(SelArgs a)
         sample_and_pivot<IS_F32, LARGEST>(a, st, sm);
         block_sweep<IS_F32, LARGEST>(a, st, sm);
     }
-}
-
-// Single-pass look-back (run by wave 0): publish the tile's counts (flag 1),
-// add predecessors' counts 64 tiles at a time until a tile with an inclusive
-// prefix (flag 2) is met, publish this tile's inclusive prefix.  Status word =
-// flag << 32 | value, cleared to 0 before the sweep.
-__device__ __forceinline__ void lookback(u64 *sa, u64 *sb, u32 tile, u32 agg_a, u32 agg_b,
-                         u32 &ex_a, u32 &ex_b)
-{
-    constexpr u64 F_AGG = 1ull << 32, F_INC = 2ull << 32;
-    const u32 l = lane_id();
-    if (tile == 0) {
-        if (l == 0) {
-            st_status(&sa[0], F_INC | agg_a);
-            st_status(&sb[0], F_INC | agg_b);
-        }
-        ex_a = ex_b = 0;
-        return;
-    }
-    if (l == 0) {
-        st_status(&sa[tile], F_AGG | agg_a);
-        st_status(&sb[tile], F_AGG | agg_b);
-    }
-    u32 ea = 0, eb = 0;
-    bool da = false, db = false;
-    i64 pred = (i64)tile - 1;
-    while (!(da && db)) {
-        const i64 t = pred - (i64)l;
-        u64 wa = F_INC, wb = F_INC;
-        if (t >= 0) {
-            for (;;) {
-                if (!da) wa = ld_status(&sa[t]);
-                if (!db) wb = ld_status(&sb[t]);
-                if ((wa >> 32) != 0 && (wb >> 32) != 0) break;
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
-        if (!da) {
-            const u64 inc = ballot((wa >> 32) == 2);
-            const u32 val = (u32)wa;
-            if (inc) {
-                const int f = __ffsll((unsigned long long)inc) - 1;
-                ea += wave_sum_u32((int)l <= f ? val : 0u);
-                da = true;
-            } else {
-                ea += wave_sum_u32(val);
-            }
-        }
-        if (!db) {
-            const u64 inc = ballot((wb >> 32) == 2);
-            const u32 val = (u32)wb;
-            if (inc) {
-                const int f = __ffsll((unsigned long long)inc) - 1;
-                eb += wave_sum_u32((int)l <= f ? val : 0u);
-                db = true;
-            } else {
-                eb += wave_sum_u32(val);
-            }
-        }
-        pred -= WAVE;
-    }
-    if (l == 0) {
-        st_status(&sa[tile], F_INC | (u64)(ea + agg_a));
-        st_status(&sb[tile], F_INC | (u64)(eb + agg_b));
-    }
-    ex_a = ea;
-    ex_b = eb;
 }
 
 // ---------------------------------------------------------------------------
@@ -647,19 +635,17 @@ __device__ __forceinline__ void classify(u32 x, u32 i, const Piv &p, u64 &mbelow
     }
 }
 
-// LDS ring shared by the control wave and the data waves of a sweep workgroup.
-struct SwSlot {
-    u32 mask[SW_DW][64][4];     // data wave, column: a mask (lo, hi), b mask (lo, hi)
-    u32 stash[SW_DW][SW_STASH]; // ords of the tile's b elements, per data wave, in order
-    u32 cnt[SW_DW];             // per data wave: |a| | |b| << 16
-    u32 off[SW_DW];             // per data wave: offset inside the tile (a | b << 16)
-    u32 ex_a, ex_b;             // the tile's exclusive prefix
-    u32 tile_next;              // tile id handed to the data waves two tiles ahead
-    u32 sig;                    // data waves that have stashed this tile
+// LDS of a sweep workgroup: per data wave two wave-tile slots.
+struct WSlot {
+    u32 mask[64][4];            // lane j: column j's a mask (lo, hi) and b mask (lo, hi)
+    u64 stash[SW_STASH];        // b elements of the wave-tile in order: ord << 32 | position
+    u32 cnt;                    // |a| | |b| << 16 of the wave-tile
+    u32 base_a, base_b;         // reserved output positions (relative to the round's start)
+    u32 state;                  // 0 free, 1 counted (posted), 2 space reserved
 };
 struct SwShared {
-    SwSlot slot[2];
-    u32 ready;                  // tiles (in this workgroup's order) whose prefix is known
+    WSlot slot[SW_DW][2];
+    u32 done;                   // data waves that have finished the sweep
 };
 
 __device__ __forceinline__ u32 lds_acquire(u32 *p)
@@ -671,90 +657,83 @@ __device__ __forceinline__ void lds_release(u32 *p, u32 v)
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// One sweep workgroup.  Wave 0 (control) takes tickets, waits until the data
-// waves have counted a tile, turns the per-wave counts into offsets, runs the
-// look-back and publishes the tile's prefix.  Waves 1..15 (data) each own
-// 64 * COLS consecutive elements of a tile; per tile they classify and count
-// (pass 1), keep the column masks and the b elements' ords in LDS, issue the
-// loads of their next tile, and then write the previous tile (pass 2) once its
-// prefix is known -- so the look-back and the writes overlap the next loads.
+// One sweep workgroup: wave 0 reserves output space, waves 1..15 stream.
+//
+// Data wave w owns the wave-tiles w, w + W, w + 2W, ... (W = data waves in
+// the grid); a wave-tile is 64 * COLS consecutive elements, element (j, lane)
+// at base + 64 j + lane.  Per wave-tile it classifies and counts (pass 1),
+// keeps the a masks and the b pairs (compacted, in order) in LDS and posts
+// the counts; once the control wave has reserved the wave-tile's output
+// ranges it writes the positions of a and the pairs of b (pass 2), and draws
+// the next round's sample from the compacted pairs.  Pass 2 of a wave-tile
+// runs after pass 1 of the next one, so the reservation (one global atomic on
+// a 64-bit counter |a| << 32 | |b| per batch of posted wave-tiles) never
+// stalls the stream.  Wave-tiles of one workgroup never wait for another
+// workgroup.  Inside a wave-tile the output is in sequence order; the order of
+// the wave-tiles' ranges follows the reservations.
 template <int KIND, bool IS_F32, bool LARGEST, bool FAST>
-__device__ __forceinline__ void sweep_pipe(const SelArgs &a, State *st, const Piv &p, u32 n,
-                                           u32 src, u32 tag, SwShared &sh)
+__device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const Piv &p, u32 n,
+                                            u32 src, u32 tag, SwShared &sh)
 {
     constexpr int COLS = KIND == 2 ? SW_COLS_BAND : SW_COLS_IN;
     constexpr u32 WSPAN = (u32)WAVE * COLS;
-    constexpr u32 TILE = (u32)SW_DW * WSPAN;
-    const u32 ntiles = (u32)(((u64)n + TILE - 1) / TILE);
     const u32 lane = lane_id();
     const u32 w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
 
     if (w == 0) {
-        // ---------------- control wave ----------------
-        u64 *sa = a.stat + (u64)(tag & 1u) * 2 * a.ntiles_max;
-        u64 *sb = sa + a.ntiles_max;
-        u64 *nx = a.stat + (u64)((tag + 1u) & 1u) * 2 * a.ntiles_max;
-        u32 *ctr = &st->tickets[0];
-        u32 t0 = 0, t1 = 0, pref = 0;
-        if (lane == 0) {
-            t0 = atomicAdd(ctr, 1u);
-            t1 = atomicAdd(ctr, 1u);
-            pref = atomicAdd(ctr, 1u);
-            sh.slot[0].tile_next = t0;
-            sh.slot[1].tile_next = t1;
-            sh.slot[0].sig = 0u;
-            sh.slot[1].sig = 0u;
-            sh.ready = 0u;
-        }
-        u32 cur = __shfl(t0, 0, WAVE), nxt = __shfl(t1, 0, WAVE);
+        // ---------------- control wave: batch reservations ----------------
+        if (lane == 0) sh.done = 0u;
         __syncthreads();
-        for (u32 i = 0; cur < ntiles; ++i) {
-            SwSlot &S = sh.slot[i & 1u];
-            while (lds_acquire(&S.sig) < (u32)SW_DW) __builtin_amdgcn_s_sleep(1);
-            const u32 c = lane < (u32)SW_DW ? S.cnt[lane] : 0u;
-            const u32 inc = wave_incl_scan(c);
-            if (lane < (u32)SW_DW) S.off[lane] = inc - c;
-            const u32 tot = __shfl(inc, SW_DW - 1, WAVE);
-            u32 ea, eb;
-            lookback(sa, sb, cur, tot & 0xFFFFu, tot >> 16, ea, eb);
-            const u32 after = __shfl(pref, 0, WAVE);   // tile id two ahead
-            if (lane == 0) {
-                S.ex_a = ea;
-                S.ex_b = eb;
-                if (cur == ntiles - 1) {
-                    st->na = ea + (tot & 0xFFFFu);
-                    st->nb = eb + (tot >> 16);
+        u64 *resv = &st->resv;
+        for (;;) {
+            const bool mine = lane < 2u * SW_DW;
+            WSlot *S = &sh.slot[mine ? lane >> 1 : 0][lane & 1u];
+            const bool posted = mine && lds_acquire(&S->state) == 1u;
+            const u64 m = ballot(posted);
+            if (m) {
+                const u32 c = posted ? S->cnt : 0u;
+                const u32 ca = c & 0xFFFFu, cb = c >> 16;
+                const u32 ia = wave_incl_scan(ca), ib = wave_incl_scan(cb);
+                const u32 ta = __shfl(ia, WAVE - 1, WAVE), tb = __shfl(ib, WAVE - 1, WAVE);
+                u64 base = 0;
+                if (lane == 0)
+                    base = atomicAdd((unsigned long long *)resv, ((u64)ta << 32) | tb);
+                const u32 bh = __shfl((u32)(base >> 32), 0, WAVE), bl = __shfl((u32)base, 0, WAVE);
+                if (posted) {
+                    S->base_a = bh + ia - ca;
+                    S->base_b = bl + ib - cb;
+                    lds_release(&S->state, 2u);
                 }
-                nx[cur] = 0ull;                     // the next sweep's status words
-                nx[a.ntiles_max + cur] = 0ull;
-                S.sig = 0u;
-                S.tile_next = after;
-                lds_release(&sh.ready, i + 1);
-                pref = atomicAdd(ctr, 1u);
+            } else {
+                if (lds_acquire(&sh.done) == (u32)SW_DW) break;
+                __builtin_amdgcn_s_sleep(2);
             }
-            cur = nxt;
-            nxt = after;
         }
         return;
     }
 
     // ---------------- data waves ----------------
     const u32 dw = w - 1;
+    if (lane == 0) {
+        sh.slot[dw][0].state = 0u;
+        sh.slot[dw][1].state = 0u;
+    }
+    __syncthreads();
     const u64 cursor = st->cursor;
+    const u64 hs_T = st->hs_T;
     const u32 di = (src == 1) ? 1u : 0u;
     u32 *__restrict__ dord = a.band_ord[di];
     u32 *__restrict__ didx = a.band_idx[di];
     const u32 *__restrict__ sord = KIND == 2 ? a.band_ord[src - 1] : a.keys;
     const u32 *__restrict__ sidx = KIND == 2 ? a.band_idx[src - 1] : a.keys;
     const bool wkeys = (a.flags & TOPK_WRITE_KEYS) && a.out_keys;
-    __syncthreads();
-    u32 cur = __builtin_amdgcn_readfirstlane(sh.slot[0].tile_next);
+    const u32 nwt = (u32)(((u64)n + WSPAN - 1) / WSPAN);
+    const u32 stride = gridDim.x * (u32)SW_DW;
     u32 x[COLS], ix[COLS];
 
-    // loads of this wave's part of `tile` (elements past n read as 0, never classified)
-    auto issue = [&](u32 tile) {
-        const u64 wb = (u64)tile * TILE + (u64)dw * WSPAN;
-        const int rem = wb >= (u64)n ? 0 : (int)((u64)n - wb < WSPAN ? (u64)n - wb : WSPAN);
+    auto issue = [&](u32 wt) {
+        const u64 wb = (u64)wt * WSPAN;
+        const int rem = (u64)n - wb < WSPAN ? (int)((u64)n - wb) : (int)WSPAN;
         const u32 *__restrict__ pw = sord + wb;
         const u32 *__restrict__ pi = sidx + wb;
         u32 ln = lane;
@@ -766,16 +745,17 @@ __device__ __forceinline__ void sweep_pipe(const SelArgs &a, State *st, const Pi
             if (KIND == 2) ix[j] = ok ? __builtin_nontemporal_load(pi + j * WAVE + ln) : 0u;
         }
     };
-    if (cur < ntiles) issue(cur);
 
+    u32 cur = blockIdx.x * (u32)SW_DW + dw;
+    if (cur < nwt) issue(cur);
     bool have_prev = false;
     u32 prev = 0;
-    for (u32 i = 0;; ++i) {
-        SwSlot &S = sh.slot[i & 1u];
-        if (cur < ntiles) {
-            // pass 1: classify, count, keep masks (lane j holds column j) and b ords
-            const u64 wb = (u64)cur * TILE + (u64)dw * WSPAN;
-            const int rem = wb >= (u64)n ? 0 : (int)((u64)n - wb < WSPAN ? (u64)n - wb : WSPAN);
+    for (u32 it = 0;; ++it) {
+        if (cur < nwt) {
+            // pass 1
+            WSlot &S = sh.slot[dw][it & 1u];
+            const u64 wb = (u64)cur * WSPAN;
+            const int rem = (u64)n - wb < WSPAN ? (int)((u64)n - wb) : (int)WSPAN;
             const u32 ib = (u32)wb;
             u32 ln = lane;
             asm volatile("" : "+v"(ln));
@@ -791,53 +771,52 @@ __device__ __forceinline__ void sweep_pipe(const SelArgs &a, State *st, const Pi
                     m0 = (u32)ma; m1 = (u32)(ma >> 32);
                     m2 = (u32)mb; m3 = (u32)(mb >> 32);
                 }
-                if (KIND != 2 && mb) {
+                if (mb) {
                     if ((mb >> ln) & 1ull) {
                         const u32 q = tb + mbcnt(mb);
-                        if (q < (u32)SW_STASH)
-                            S.stash[dw][q] = KIND == 0 ? key_ord<true, LARGEST>(x[j]) : (LARGEST ? ~x[j] : x[j]);
+                        if (q < (u32)SW_STASH) {
+                            const u32 o = KIND == 0 ? key_ord<true, LARGEST>(x[j])
+                                        : KIND == 1 ? (LARGEST ? ~x[j] : x[j]) : x[j];
+                            S.stash[q] = pack(o, ie);
+                        }
                     }
                 }
                 ta += (u32)__popcll(ma);
                 tb += (u32)__popcll(mb);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            *(uint4 *)&S.mask[dw][ln][0] = make_uint4(m0, m1, m2, m3);
+            *(uint4 *)&S.mask[ln][0] = make_uint4(m0, m1, m2, m3);
             if (lane == 0) {
-                S.cnt[dw] = ta | (tb << 16);
-                __hip_atomic_fetch_add(&S.sig, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                S.cnt = ta | (tb << 16);
+                lds_release(&S.state, 1u);
             }
         }
-        if (have_prev)
-            while (lds_acquire(&sh.ready) < i) __builtin_amdgcn_s_sleep(1);
-        u32 nxt = ntiles;
-        if (cur < ntiles) nxt = __builtin_amdgcn_readfirstlane(sh.slot[(i + 1) & 1u].tile_next);
-        if (nxt < ntiles) issue(nxt);
         if (have_prev) {
-            // pass 2 of the previous tile: write a's positions and b's pairs
-            SwSlot &P = sh.slot[(i - 1) & 1u];
-            const u64 wb = (u64)prev * TILE + (u64)dw * WSPAN;
-            const u32 offp = P.off[dw];
-            const u32 cb = P.cnt[dw] >> 16;
-            u64 pa = cursor + P.ex_a + (offp & 0xFFFFu);
-            u64 pb = (u64)P.ex_b + (offp >> 16);
-            u32 ln = lane;
-            asm volatile("" : "+v"(ln));
-            const uint4 mm = *(const uint4 *)&P.mask[dw][ln][0];
-            u32 sbr = 0;
-            const bool stashed = KIND != 2 && cb <= (u32)SW_STASH;
+            // pass 2 of the previous wave-tile
+            WSlot &P = sh.slot[dw][(it - 1) & 1u];
+            while (lds_acquire(&P.state) != 2u) __builtin_amdgcn_s_sleep(1);
+            const u64 wb = (u64)prev * WSPAN;
             const u32 *__restrict__ pw = sord + wb;
             const u32 *__restrict__ pi = sidx + wb;
+            const u32 cb = P.cnt >> 16;
+            u64 pa = cursor + P.base_a;
+            const u64 pb0 = P.base_b;
+            u32 ln = lane;
+            asm volatile("" : "+v"(ln));
+            const uint4 mm = *(const uint4 *)&P.mask[ln][0];
+            const bool stashed = cb <= (u32)SW_STASH;
+            u64 pb = pb0;
 #pragma unroll
             for (int j = 0; j < COLS; ++j) {
                 const u64 ma = ((u64)(u32)__builtin_amdgcn_readlane(mm.y, j) << 32) |
                                (u32)__builtin_amdgcn_readlane(mm.x, j);
-                const u64 mb = ((u64)(u32)__builtin_amdgcn_readlane(mm.w, j) << 32) |
+                const u64 mb = stashed ? 0ull
+                             : ((u64)(u32)__builtin_amdgcn_readlane(mm.w, j) << 32) |
                                (u32)__builtin_amdgcn_readlane(mm.z, j);
                 if (ma | mb) {
                     const bool ia = (ma >> ln) & 1ull, ibm = (mb >> ln) & 1ull;
-                    // values not kept in LDS are read again (these columns were just loaded)
-                    const bool need = (KIND == 2 && (ia || ibm)) || (ibm && !stashed) || (ia && wkeys);
+                    // values not kept in LDS are read again (this wave-tile was just loaded)
+                    const bool need = ibm || (ia && (KIND == 2 || wkeys));
                     u32 xv = 0, iv = 0;
                     if (need) {
                         xv = pw[j * WAVE + ln];
@@ -852,27 +831,50 @@ __device__ __forceinline__ void sweep_pipe(const SelArgs &a, State *st, const Pi
                         }
                     }
                     if (ibm) {
-                        const u32 r = mbcnt(mb);
-                        const u64 q = pb + r;
-                        if (q < a.band_cap) {
-                            dord[q] = stashed ? P.stash[dw][sbr + r]
-                                    : KIND == 0 ? key_ord<true, LARGEST>(xv)
+                        // b overflowed the LDS stash: write it from the data directly
+                        const u32 o = KIND == 0 ? key_ord<true, LARGEST>(xv)
                                     : KIND == 1 ? (LARGEST ? ~xv : xv) : xv;
+                        const u64 q = pb + mbcnt(mb);
+                        if (q < a.band_cap) {
+                            dord[q] = o;
                             didx[q] = ie;
                         }
                     }
+                    if (mb) {
+                        const u32 o = KIND == 0 ? key_ord<true, LARGEST>(xv)
+                                    : KIND == 1 ? (LARGEST ? ~xv : xv) : xv;
+                        sample_append(a, st, ibm && hash_taken(a.seed, tag + 1, ie, hs_T), pack(o, ie));
+                    }
                     pa += (u64)__popcll(ma);
                     pb += (u64)__popcll(mb);
-                    sbr += (u32)__popcll(mb);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
+            if (stashed) {
+                // b from the stash: contiguous, coalesced writes
+                for (u32 q0 = 0; q0 < cb; q0 += WAVE) {
+                    const u32 q = q0 + ln;
+                    const bool have = q < cb;
+                    const u64 e = have ? P.stash[q] : 0ull;
+                    const u64 dst = pb0 + q;
+                    if (have && dst < a.band_cap) {
+                        dord[dst] = (u32)(e >> 32);
+                        didx[dst] = (u32)e;
+                    }
+                    sample_append(a, st, have && hash_taken(a.seed, tag + 1, (u32)e, hs_T), e);
+                }
+            }
+            if (lane == 0) lds_release(&P.state, 0u);
         }
-        if (cur >= ntiles) break;
+        if (cur >= nwt) break;
+        const u32 nxt = cur + stride;
+        if (nxt < nwt) issue(nxt);
         have_prev = true;
         prev = cur;
         cur = nxt;
     }
+    if (lane == 0)
+        __hip_atomic_fetch_add(&sh.done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // FIRST only names the instance enqueued for the first round (which reads
@@ -886,13 +888,13 @@ __global__ __launch_bounds__(SW_THREADS) void k_sweep(SelArgs a)
     __shared__ SwShared sh;
     const Piv p = load_pivots<IS_F32, LARGEST>(st);
     if (src != 0)
-        sweep_pipe<2, IS_F32, LARGEST, true>(a, st, p, n, src, tag, sh);
+        sweep_waves<2, IS_F32, LARGEST, true>(a, st, p, n, src, tag, sh);
     else if (!IS_F32)
-        sweep_pipe<1, IS_F32, LARGEST, true>(a, st, p, n, src, tag, sh);
+        sweep_waves<1, IS_F32, LARGEST, true>(a, st, p, n, src, tag, sh);
     else if (p.fast)
-        sweep_pipe<0, IS_F32, LARGEST, true>(a, st, p, n, src, tag, sh);
+        sweep_waves<0, IS_F32, LARGEST, true>(a, st, p, n, src, tag, sh);
     else
-        sweep_pipe<0, IS_F32, LARGEST, false>(a, st, p, n, src, tag, sh);
+        sweep_waves<0, IS_F32, LARGEST, false>(a, st, p, n, src, tag, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -923,7 +925,7 @@ static hipError_t launch_impl(SelArgs a, const SelLaunch &L, hipStream_t s, Kern
         return hipGetLastError();
     }
     t = tm_begin(tm, KT_PIVOT_FIRST, s);
-    hipLaunchKernelGGL((k_pivot<F, LG>), dim3(1 + L.clear_blocks), dim3(PV_THREADS), 0, s, a);
+    hipLaunchKernelGGL((k_pivot<F, LG>), dim3(1), dim3(PV_THREADS), 0, s, a);
     tm_end(tm, t, s);
     a.first = 0;
     for (int r = 0; r < L.r_fast; ++r) {

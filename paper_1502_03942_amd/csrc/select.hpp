@@ -16,9 +16,9 @@ constexpr int SW_COLS_IN = 64;                 // input keys per data-wave lane 
 constexpr int SW_COLS_BAND = 32;               // band pairs per data-wave lane per tile
 constexpr int SW_TILE_IN = SW_DW * 64 * SW_COLS_IN;     // 61440 keys
 constexpr int SW_TILE_BAND = SW_DW * 64 * SW_COLS_BAND; // 30720 pairs
-constexpr int SW_STASH = 512;                  // band ords kept in LDS per data wave and tile
+constexpr int SW_STASH = 384;                  // b pairs kept in LDS per wave-tile
+constexpr int S_MAX = PV_THREADS * SEG_CAP;    // largest usable sample (16384)
 constexpr int R_TRACE = 32;                    // attempt records kept
-constexpr int NTICKET = 64;                    // ticket words kept zeroed for the sweep
 constexpr int TRACE_STRIDE = NSEG * SEG_CAP;   // sample positions per record
 
 enum : uint32_t { PH_PIVOT = 0, PH_SWEEP = 1, PH_DONE = 2, PH_ERROR = 3 };
@@ -32,12 +32,14 @@ struct RoundRec {                 // same layout as topk_round_record
 
 struct State {
     uint32_t phase, n_cur, k_cur, cursor;
-    uint32_t src, tag, c_num, pad3;
+    uint32_t src, tag, c_num, hs_ok;   // hs_ok: the sample collected by the last sweep is usable
     uint32_t na, nb, nrec, pad0;
     uint32_t l_ord, l_idx, r_ord, r_idx;
     uint32_t has_l, has_r, pad1, pad2;
+    uint64_t resv;              // sweep output reservations: |a| << 32 | |b|
+    uint64_t hs_T;              // rate of the sample drawn from b (T = rho 2^32)
+    uint32_t hs_count, pad4, pad5, pad6;   // elements taken into that sample
     RoundRec rec[R_TRACE];
-    uint32_t tickets[NTICKET];  // tickets[0]: the sweep's tile counter
 };
 
 struct SelArgs {
@@ -45,22 +47,19 @@ struct SelArgs {
     uint32_t n, k, flags;
     uint32_t *out_idx, *out_keys, *kth_key, *kth_idx, *status;
     State *st;
-    uint64_t *stat;             // [2 parities][2 (a,b)][ntiles_max]
-    uint32_t ntiles_max;
     uint32_t band_cap;
     uint32_t *band_ord[2], *band_idx[2];
     uint32_t *trace_pos;        // [R_TRACE][TRACE_STRIDE] or nullptr
+    uint64_t *hs_buf;           // [S_MAX] sample drawn while b is formed: ord << 32 | position
     uint32_t s_target, c_num0, t_fin, r_max;
     uint64_t seed;
     uint32_t first;             // first kernel of the call: initialise the state
-    uint32_t clear_words;       // first pivot kernel: status words of parity 0 to clear
 };
 
 struct SelLaunch {
     int is_f32, largest;
     int r_fast;                 // multi-workgroup rounds before the tail kernel
     int sweep_grid[8];          // workgroups per enqueued sweep
-    int clear_blocks;
 };
 
 // Optional HIP-event timing of the enqueued kernels (start/stop event pairs).

@@ -40,7 +40,7 @@ def compare(ctx, keys_np, keys, k, largest):
     assert oracle.check(keys_np, k, got, kth, kb, largest) == 0
     rc, rout, rkth, rrecs = oracle.replay(keys_np, k, largest, **replay_params(ctx, keys_np.size))
     assert rc == 0
-    assert np.array_equal(got, rout) and kth == rkth
+    assert np.array_equal(np.sort(got), np.sort(rout)) and kth == rkth
     assert ctx.trace_rounds(res) == rrecs
 
 

@@ -282,6 +282,40 @@ def test_sampler_full_rate_and_caps():
     assert pos.size == 12
 
 
+def test_hash_sampler_rate_and_independence():
+    # per-element decisions: P(taken) = T / 2^32, independent of the position
+    T = int(0.1 * 2**32)
+    taken = np.array([oracle.hash_taken(77, 3, x, T) for x in range(40000)])
+    p = taken.mean()
+    assert abs(p - 0.1) < 5 * math.sqrt(0.1 * 0.9 / taken.size)
+    # pairs of neighbours are uncorrelated
+    both = np.mean(taken[:-1] & taken[1:])
+    assert abs(both - 0.01) < 5 * math.sqrt(0.01 / taken.size)
+    # T = 0 takes nothing, T = 2^32 takes everything; another tag is another stream
+    assert not any(oracle.hash_taken(77, 3, x, 0) for x in range(100))
+    assert all(oracle.hash_taken(77, 3, x, 2**32) for x in range(100))
+    other = np.array([oracle.hash_taken(77, 4, x, T) for x in range(40000)])
+    assert 0 < np.sum(taken != other) and abs(np.mean(taken & other) - 0.01) < 0.003
+
+
+def test_hash_sampler_matches_philox_word():
+    # the decision is word 0 of Philox4x32-10 at counter (x, 0, tag, 1), key = seed
+    seed = 0x1234_5678_9ABC_DEF0
+    for x, tag in ((0, 0), (5, 1), (2**31 + 7, 9)):
+        w = int(oracle.philox4x32_10([x, 0, tag, 1], [seed & 0xFFFFFFFF, seed >> 32])[0])
+        assert oracle.hash_taken(seed, tag, x, w + 1) and not oracle.hash_taken(seed, tag, x, w)
+
+
+def test_band_threshold_hand_worked():
+    # pivots cover ranks [bot, top): expected b = n (top - bot) / s, rho = s_target / that
+    # n = 2^28, s = 4096, lo = 1919, hi = 2177: b ~ 2^28 * 259 / 4096 = 16973824
+    assert oracle.band_threshold(2**28, 4096, 1919, 2177, 4096) == (4096 << 32) // 16973824
+    # no lower pivot (lo < 0): bot = 0; hi = 6 -> top = 7: b ~ 2^28 * 7 / 4096 = 458752
+    assert oracle.band_threshold(2**28, 4096, -5, 6, 4096) == (4096 << 32) // 458752
+    # no pivots at all: b ~ n
+    assert oracle.band_threshold(1000, 10, -3, 12, 4096) == (4096 << 32) // 1000
+
+
 # ---------------------------------------------------------------- pivots ----
 
 def test_pivot_ranks_hand_worked():
@@ -376,7 +410,7 @@ def test_replay_wide_band_halves_spread():
     # subproblem; halving c restores progress
     keys = synth.small_alphabet_u32(20000, 5, 4)
     rc, out, kth, recs = oracle.replay(keys, 10000, s_target=16, c_num=16, nseg=1024,
-                                       seg_cap=16, t_fin=64, r_max=32, band_cap=20000, seed=5)
+                                       seg_cap=16, t_fin=512, r_max=32, band_cap=20000, seed=5)
     assert rc == 0
     assert not recs[0]["ok"] and recs[0]["nb"] == recs[0]["n_cur"]
     assert recs[1]["c_num"] == 8
