@@ -18,6 +18,8 @@
 //
 // The host enqueues k_pivot, k_sweep, [k_pivot, k_sweep]..., k_tail once; the
 // round state lives in device memory, so no round trip to the host occurs.
+#include <type_traits>
+
 #include "common.hpp"
 #include "select.hpp"
 #include "../../include/topk.h"
@@ -557,34 +559,42 @@ __global__ __launch_bounds__(PV_THREADS) void k_tail(SelArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// The hot loop (§2 Algorithm's partition and reduction; §10 notes that the
-// partition dominates the running time).
+// The hot loop: partition of the current input into a, b, c (§2 Algorithm;
+// the partition is the part of the running time that scales with n).
 //
-// Geometry.  A workgroup of 16 waves takes one tile; wave w owns 64 * ITEMS
-// consecutive elements of it and element (j, lane) of the wave is
-// wave_base + 64 j + lane, so every load instruction reads 256 contiguous
-// bytes and the stable (sequence-order) position of an element inside its
-// wave is a running count plus one mbcnt.
+// Geometry.  A wave-tile is 64 * COLS consecutive elements; element (j, lane)
+// is base + 64 j + lane, so every load instruction reads 256 contiguous bytes
+// and the rank of an element among the a (or b) elements of its wave-tile, in
+// sequence order, is a count over the columns before j plus one mbcnt.  Data
+// wave dw of workgroup g takes wave-tiles (t G + g) W + dw, t = 0, 1, ...
+// (W data waves per workgroup, G workgroups); iteration t of all data waves
+// of a workgroup is its generation t.
 //
-// Classification.  Keys are compared with the pivots in their own type: f32
-// keys as floats (with -0 == +0 and NaN above everything expressed through
-// the IEEE predicates), u32 keys and band ords as integers; the position
-// breaks ties only when a key equals a pivot.  A compare result is already
-// the wave's ballot, so |a| and |b| per wave are scalar popcounts.  Pass 1
-// counts and notes which columns j hold any element of a or b; after the
-// tile's offsets are known, pass 2 recomputes those columns and writes.
+// Classification.  Pass 1 compares each key with the pivots strictly: below
+// l goes to a, above r to c, the rest (including keys equal to a pivot) to b.
+// f32 keys are compared as floats while no pivot is NaN (-0 == +0 and NaN
+// above all follow from the IEEE predicates), else through their order
+// transform; u32 keys and band ords as integers.  A key equal to a pivot
+// belongs to a or c by its position (§2: ties are broken by the object), so a
+// wave-tile whose b holds such a key classifies again with positions; that
+// happens for the few wave-tiles holding a pivot unless keys repeat.
 //
-// Offsets.  Tiles are taken in order from one atomic ticket (fetched one tile
-// ahead) and their prefix comes from a single-pass decoupled look-back
-// (Merrill & Garland 2016): every tile a look-back waits for is held by a
-// running workgroup, so the sweep completes for any grid size.
+// Per lane, the a-membership of the lane's 64 elements is kept as bits in
+// two registers (a transposed mask), so pass 1 spends two compares per
+// column on elements outside b.  b is compacted in sequence order into an
+// LDS stash.  Pass 2 of a wave-tile runs after pass 1 of the next one, once
+// the control wave has reserved its output ranges: it rebuilds each column's
+// a-mask from the bits, writes the positions of a, and copies the stash to
+// the band with coalesced stores while drawing the next round's sample from
+// it (element-wise Philox decisions).  A stash overflow reloads the wave-tile.
 // ---------------------------------------------------------------------------
 struct Piv {
     u32 lo, li, ro, ri;     // pivot ords and positions (selection order); absent
                             // pivots are sentinels no (ord, position) pair passes
-    float lv, rv;           // f32 input: pivot values
-    u64 hlm, hrm;           // all ones if the pivot is present, else 0
-    bool fast;              // f32 input: neither pivot is NaN
+    float lv, rv;           // f32 input and fast: pivot values (an absent pivot
+                            // that the fast compare allows is -inf)
+    bool hl, hr;            // pivot present
+    bool fast;              // f32 input: compare as floats (see load_pivots)
 };
 
 __device__ __forceinline__ u32 bits_from_ord(u32 o)
@@ -592,60 +602,106 @@ __device__ __forceinline__ u32 bits_from_ord(u32 o)
     return (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
 }
 
+// The float compare needs non-NaN pivots and, in smallest order, a right
+// pivot (no float threshold leaves NaN out of c), in largest order a left
+// pivot (none leaves NaN out of a).  The other absent pivot becomes -inf:
+// nothing is below it (smallest) and nothing after it (largest).
 template <bool IS_F32, bool LARGEST>
 __device__ __forceinline__ Piv load_pivots(const State *st)
 {
     Piv p;
-    const bool hl = st->has_l != 0, hr = st->has_r != 0;
-    p.hlm = hl ? ~0ull : 0ull;
-    p.hrm = hr ? ~0ull : 0ull;
-    p.lo = hl ? st->l_ord : 0u;
-    p.li = hl ? st->l_idx : 0u;
-    p.ro = hr ? st->r_ord : 0xFFFFFFFFu;
-    p.ri = hr ? st->r_idx : 0xFFFFFFFFu;
-    p.fast = true;
+    p.hl = st->has_l != 0;
+    p.hr = st->has_r != 0;
+    p.lo = p.hl ? st->l_ord : 0u;
+    p.li = p.hl ? st->l_idx : 0u;
+    p.ro = p.hr ? st->r_ord : 0xFFFFFFFFu;
+    p.ri = p.hr ? st->r_idx : 0xFFFFFFFFu;
+    p.fast = false;
     p.lv = p.rv = 0.f;
     if (IS_F32) {
-        const u32 ls = LARGEST ? ~p.lo : p.lo, rs = LARGEST ? ~p.ro : p.ro;
-        p.fast = (!hl || ls != 0xFFFFFFFFu) && (!hr || rs != 0xFFFFFFFFu);
-        p.lv = __uint_as_float(bits_from_ord(ls));
-        p.rv = __uint_as_float(bits_from_ord(rs));
+        const u32 ls = LARGEST ? ~p.lo : p.lo, rs = LARGEST ? ~p.ro : p.ro;  // ascending ords
+        const bool lnan = p.hl && ls == 0xFFFFFFFFu, rnan = p.hr && rs == 0xFFFFFFFFu;
+        p.fast = !lnan && !rnan && (LARGEST ? p.hl : p.hr);
+        const float ninf = __uint_as_float(0xFF800000u);
+        p.lv = p.hl ? __uint_as_float(bits_from_ord(ls)) : ninf;
+        p.rv = p.hr ? __uint_as_float(bits_from_ord(rs)) : ninf;
     }
     return p;
 }
 
-// Lane masks of the elements below l (part a) and above r (part c) in one
-// column, branch-free.  KIND 0: x = f32 key bits compared as floats (FAST: no
-// NaN pivot; then -0 == +0 and NaN above all follow from the IEEE predicates),
-// 1: x = u32 key, 2: x = band ord; KIND 0 without FAST compares ords.
-// i = the element's position (it breaks ties with a pivot).
-template <int KIND, bool LARGEST, bool FAST>
-__device__ __forceinline__ void classify(u32 x, u32 i, const Piv &p, u64 &mbelow, u64 &mabove)
+// Selection-order ord of an element as loaded.  KIND 0: f32 key bits, 1: u32
+// key, 2: band ord (already one).
+template <int KIND, bool LARGEST>
+__device__ __forceinline__ u32 ord_of(u32 x)
+{
+    return KIND == 0 ? key_ord<true, LARGEST>(x) : KIND == 1 ? (LARGEST ? ~x : x) : x;
+}
+
+// Membership of one element: ia = in a, ic = in c.  TIES: break ties with a
+// pivot by position i (else keys equal to a pivot are in b).
+template <int KIND, bool LARGEST, bool FAST, bool TIES>
+__device__ __forceinline__ void classify(u32 x, u32 i, const Piv &p, bool &ia, bool &ic)
 {
     if (KIND == 0 && FAST) {
         const float f = __uint_as_float(x);
-        const bool bl = (LARGEST ? !(f <= p.lv) : (f < p.lv)) || (f == p.lv && i < p.li);
-        const bool ab = (LARGEST ? (f < p.rv) : !(f <= p.rv)) || (f == p.rv && i > p.ri);
-        mbelow = ballot(bl) & p.hlm;
-        mabove = ballot(ab) & p.hrm;
+        ia = LARGEST ? !(f <= p.lv) : (f < p.lv);
+        ic = LARGEST ? (f < p.rv) : !(f <= p.rv);
+        if (TIES) {
+            ia = ia || (p.hl && f == p.lv && i < p.li);
+            ic = ic || (p.hr && f == p.rv && i > p.ri);
+        }
     } else {
-        const u32 o = KIND == 0 ? key_ord<true, LARGEST>(x) : KIND == 1 ? (LARGEST ? ~x : x) : x;
-        mbelow = ballot(o < p.lo || (o == p.lo && i < p.li));
-        mabove = ballot(o > p.ro || (o == p.ro && i > p.ri));
+        const u32 o = ord_of<KIND, LARGEST>(x);
+        ia = o < p.lo;
+        ic = o > p.ro;
+        if (TIES) {
+            ia = ia || (p.hl && o == p.lo && i < p.li);
+            ic = ic || (p.hr && o == p.ro && i > p.ri);
+        }
     }
+}
+
+// Does x equal a present pivot (so that its position decides its part)?
+template <int KIND, bool LARGEST, bool FAST>
+__device__ __forceinline__ bool equals_pivot(u32 x, const Piv &p)
+{
+    if (KIND == 0 && FAST) {
+        const float f = __uint_as_float(x);
+        return (p.hl && f == p.lv) || (p.hr && f == p.rv);
+    }
+    const u32 o = ord_of<KIND, LARGEST>(x);
+    return (p.hl && o == p.lo) || (p.hr && o == p.ro);
+}
+
+// f(std::integral_constant<int, J>()) for J = 0 .. N-1, unrolled.
+template <class F, int... J>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, J...>)
+{
+    (f(std::integral_constant<int, J>()), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>());
+}
+
+// mbcnt(mask) + base
+__device__ __forceinline__ u32 mbcnt_add(u64 mask, u32 base)
+{
+    return __builtin_amdgcn_mbcnt_hi((u32)(mask >> 32), __builtin_amdgcn_mbcnt_lo((u32)mask, base));
 }
 
 // LDS of a sweep workgroup: per data wave two wave-tile slots.
 struct WSlot {
-    u32 mask[64][4];            // lane j: column j's a mask (lo, hi) and b mask (lo, hi)
-    u64 stash[SW_STASH];        // b elements of the wave-tile in order: ord << 32 | position
+    u64 stash[SW_STASH + WAVE]; // b of the wave-tile in sequence order: key bits
+                                // (band: ord) << 32 | position; a column is
+                                // stashed whole while fewer than SW_STASH precede it
     u32 cnt;                    // |a| | |b| << 16 of the wave-tile
     u32 base_a, base_b;         // reserved output positions (relative to the round's start)
     u32 state;                  // 0 free, 1 counted (posted), 2 space reserved
 };
 struct SwShared {
-    WSlot slot[SW_DW][2];
-    u32 done;                   // data waves that have finished the sweep
+    WSlot slot[SW_DW][2];       // [data wave][generation parity]
 };
 
 __device__ __forceinline__ u32 lds_acquire(u32 *p)
@@ -657,20 +713,12 @@ __device__ __forceinline__ void lds_release(u32 *p, u32 v)
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// One sweep workgroup: wave 0 reserves output space, waves 1..15 stream.
-//
-// Data wave w owns the wave-tiles w, w + W, w + 2W, ... (W = data waves in
-// the grid); a wave-tile is 64 * COLS consecutive elements, element (j, lane)
-// at base + 64 j + lane.  Per wave-tile it classifies and counts (pass 1),
-// keeps the a masks and the b pairs (compacted, in order) in LDS and posts
-// the counts; once the control wave has reserved the wave-tile's output
-// ranges it writes the positions of a and the pairs of b (pass 2), and draws
-// the next round's sample from the compacted pairs.  Pass 2 of a wave-tile
-// runs after pass 1 of the next one, so the reservation (one global atomic on
-// a 64-bit counter |a| << 32 | |b| per batch of posted wave-tiles) never
-// stalls the stream.  Wave-tiles of one workgroup never wait for another
-// workgroup.  Inside a wave-tile the output is in sequence order; the order of
-// the wave-tiles' ranges follows the reservations.
+// One sweep workgroup: wave 0 reserves output space, waves 1..SW_DW stream.
+// The reservation is one global atomic on a 64-bit counter |a| << 32 | |b|
+// per generation of the workgroup, so pass 2 of a wave-tile (which waits for
+// it) trails pass 1 by one wave-tile and wave-tiles of one workgroup never
+// wait for another workgroup.  Inside a generation the output is in sequence
+// order; the order of the generations' ranges follows the reservations.
 template <int KIND, bool IS_F32, bool LARGEST, bool FAST>
 __device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const Piv &p, u32 n,
                                             u32 src, u32 tag, SwShared &sh)
@@ -679,34 +727,31 @@ __device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const P
     constexpr u32 WSPAN = (u32)WAVE * COLS;
     const u32 lane = lane_id();
     const u32 w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const u32 nwt = (u32)(((u64)n + WSPAN - 1) / WSPAN);
+    const u32 stride = gridDim.x * (u32)SW_DW;
 
     if (w == 0) {
-        // ---------------- control wave: batch reservations ----------------
-        if (lane == 0) sh.done = 0u;
+        // ------------- control wave: one reservation per generation -------------
         __syncthreads();
         u64 *resv = &st->resv;
-        for (;;) {
-            const bool mine = lane < 2u * SW_DW;
-            WSlot *S = &sh.slot[mine ? lane >> 1 : 0][lane & 1u];
-            const bool posted = mine && lds_acquire(&S->state) == 1u;
-            const u64 m = ballot(posted);
-            if (m) {
-                const u32 c = posted ? S->cnt : 0u;
-                const u32 ca = c & 0xFFFFu, cb = c >> 16;
-                const u32 ia = wave_incl_scan(ca), ib = wave_incl_scan(cb);
-                const u32 ta = __shfl(ia, WAVE - 1, WAVE), tb = __shfl(ib, WAVE - 1, WAVE);
-                u64 base = 0;
-                if (lane == 0)
-                    base = atomicAdd((unsigned long long *)resv, ((u64)ta << 32) | tb);
-                const u32 bh = __shfl((u32)(base >> 32), 0, WAVE), bl = __shfl((u32)base, 0, WAVE);
-                if (posted) {
-                    S->base_a = bh + ia - ca;
-                    S->base_b = bl + ib - cb;
-                    lds_release(&S->state, 2u);
-                }
-            } else {
-                if (lds_acquire(&sh.done) == (u32)SW_DW) break;
-                __builtin_amdgcn_s_sleep(2);
+        for (u32 t = 0;; ++t) {
+            const u64 t0 = ((u64)t * gridDim.x + blockIdx.x) * (u64)SW_DW;
+            if (t0 >= nwt) break;
+            const u32 expected = (u64)nwt - t0 < (u64)SW_DW ? (u32)((u64)nwt - t0) : (u32)SW_DW;
+            const bool mine = lane < expected;
+            WSlot *S = &sh.slot[mine ? lane : 0u][t & 1u];
+            while (ballot(mine && lds_acquire(&S->state) != 1u)) __builtin_amdgcn_s_sleep(1);
+            const u32 c = mine ? S->cnt : 0u;
+            const u32 ca = c & 0xFFFFu, cb = c >> 16;
+            const u32 ia = wave_incl_scan(ca), ib = wave_incl_scan(cb);
+            const u32 ta = __shfl(ia, WAVE - 1, WAVE), tb = __shfl(ib, WAVE - 1, WAVE);
+            u64 base = 0;
+            if (lane == 0) base = atomicAdd((unsigned long long *)resv, ((u64)ta << 32) | tb);
+            const u32 bh = __shfl((u32)(base >> 32), 0, WAVE), bl = __shfl((u32)base, 0, WAVE);
+            if (mine) {
+                S->base_a = bh + ia - ca;
+                S->base_b = bl + ib - cb;
+                lds_release(&S->state, 2u);
             }
         }
         return;
@@ -727,154 +772,212 @@ __device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const P
     const u32 *__restrict__ sord = KIND == 2 ? a.band_ord[src - 1] : a.keys;
     const u32 *__restrict__ sidx = KIND == 2 ? a.band_idx[src - 1] : a.keys;
     const bool wkeys = (a.flags & TOPK_WRITE_KEYS) && a.out_keys;
-    const u32 nwt = (u32)(((u64)n + WSPAN - 1) / WSPAN);
-    const u32 stride = gridDim.x * (u32)SW_DW;
     u32 x[COLS], ix[COLS];
 
+    // Loads of one wave-tile; only the last (ragged) wave-tile tests bounds.
     auto issue = [&](u32 wt) {
         const u64 wb = (u64)wt * WSPAN;
-        const int rem = (u64)n - wb < WSPAN ? (int)((u64)n - wb) : (int)WSPAN;
         const u32 *__restrict__ pw = sord + wb;
         const u32 *__restrict__ pi = sidx + wb;
         u32 ln = lane;
         asm volatile("" : "+v"(ln));
+        if ((u64)n - wb >= WSPAN) {
 #pragma unroll
-        for (int j = 0; j < COLS; ++j) {
-            const bool ok = (int)ln < rem - j * WAVE;
-            x[j] = ok ? __builtin_nontemporal_load(pw + j * WAVE + ln) : 0u;
-            if (KIND == 2) ix[j] = ok ? __builtin_nontemporal_load(pi + j * WAVE + ln) : 0u;
+            for (int j = 0; j < COLS; ++j) {
+                x[j] = __builtin_nontemporal_load(pw + j * WAVE + ln);
+                if (KIND == 2) ix[j] = __builtin_nontemporal_load(pi + j * WAVE + ln);
+            }
+        } else {
+            int rem = (int)((u64)n - wb);
+            asm volatile("" : "+s"(rem));
+#pragma unroll
+            for (int j = 0; j < COLS; ++j) {
+                const bool ok = (int)ln < rem - j * WAVE;
+                x[j] = ok ? __builtin_nontemporal_load(pw + j * WAVE + ln) : 0u;
+                if (KIND == 2) ix[j] = ok ? __builtin_nontemporal_load(pi + j * WAVE + ln) : 0u;
+            }
         }
+    };
+
+    // Pass 1 over the loaded (full) wave-tile, ties left in b: a-bits (column
+    // j in bit 31 - j % 32 of A[j / 32]), b into the stash; returns |b|.
+    auto pass1 = [&](WSlot &S, u32 ib, u32 &A0, u32 &A1) -> u32 {
+        u32 ln = lane;
+        asm volatile("" : "+v"(ln));
+        u32 a0 = 0, a1 = 0, tb = 0;
+        static_for<COLS>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            bool ia, ic;
+            classify<KIND, LARGEST, FAST, false>(x[j], 0u, p, ia, ic);
+            if (j < 32) a0 = a0 + a0 + (u32)ia;
+            else        a1 = a1 + a1 + (u32)ia;
+            asm volatile("" : "+v"(a0), "+v"(a1));   // materialize now (else every mask stays live)
+            const u64 mb = ~(ballot(ia) | ballot(ic));
+            if (mb) {
+                if (tb < (u32)SW_STASH && !(ia || ic)) {
+                    u32 xk = x[j];
+                    asm volatile("" : "+v"(xk));    // a register of its own (else keys load into pairs)
+                    const u32 ie = KIND == 2 ? ix[j] : ib + (u32)(j * WAVE) + ln;
+                    S.stash[mbcnt_add(mb, tb)] = pack(xk, ie);
+                }
+                tb += (u32)__popcll(mb);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        });
+        A0 = a0;
+        A1 = a1;
+        return tb;
+    };
+
+    // Pass 1 with ties broken by position, reading the wave-tile again one
+    // column at a time (wave-tiles with a key equal to a pivot, and the last).
+    auto pass1_ties = [&](WSlot &S, u64 wb, u32 &A0, u32 &A1) -> u32 {
+        const u32 *__restrict__ pw = sord + wb;
+        const u32 *__restrict__ pi = sidx + wb;
+        u32 a0 = 0, a1 = 0, tb = 0;
+#pragma unroll 1
+        for (u32 j = 0; j < (u32)COLS; ++j) {
+            const u32 e = j * WAVE + lane;
+            const bool ok = wb + e < (u64)n;
+            const u32 xv = ok ? pw[e] : 0u;
+            const u32 iv = KIND == 2 ? (ok ? pi[e] : 0u) : (u32)wb + e;
+            bool ia, ic;
+            classify<KIND, LARGEST, FAST, true>(xv, iv, p, ia, ic);
+            ia = ia && ok;
+            ic = ic || !ok;
+            if (j < 32) a0 = a0 + a0 + (u32)ia;
+            else        a1 = a1 + a1 + (u32)ia;
+            const bool ibb = !(ia || ic);
+            const u64 mb = ballot(ibb);
+            if (mb) {
+                if (tb < (u32)SW_STASH && ibb) S.stash[mbcnt_add(mb, tb)] = pack(xv, iv);
+                tb += (u32)__popcll(mb);
+            }
+        }
+        if (COLS <= 32) a1 = 0;
+        A0 = a0;
+        A1 = a1;
+        return tb;
+    };
+
+    // Pass 1 with the tie and overflow checks; posts the counts.
+    auto count_tile = [&](u32 wt, WSlot &S, u32 &A0, u32 &A1) {
+        const u64 wb = (u64)wt * WSPAN;
+        u32 tb;
+        bool redo = (u64)n - wb < WSPAN;
+        if (!redo) {
+            tb = pass1(S, (u32)wb, A0, A1);
+            redo = tb > (u32)SW_STASH;
+            if (!redo && (p.hl || p.hr)) {
+                // keys equal to a pivot were left in b: look for them in the stash
+                bool eq = false;
+                for (u32 q0 = 0; q0 < tb; q0 += WAVE) {
+                    const u32 q = q0 + lane;
+                    eq = eq || (q < tb && equals_pivot<KIND, LARGEST, FAST>((u32)(S.stash[q] >> 32), p));
+                }
+                redo = ballot(eq) != 0;
+            }
+        }
+        if (redo) tb = pass1_ties(S, wb, A0, A1);
+        const u32 ta = wave_sum_u32((u32)__popc(A0) + (u32)__popc(A1));
+        if (lane == 0) {
+            S.cnt = ta | (tb << 16);
+            lds_release(&S.state, 1u);
+        }
+    };
+
+    // Pass 2: write a and b of a counted wave-tile (its loads are gone).
+    auto write_tile = [&](u32 wt, WSlot &P, u32 A0, u32 A1) {
+        while (lds_acquire(&P.state) != 2u) __builtin_amdgcn_s_sleep(1);
+        const u64 wb = (u64)wt * WSPAN;
+        const u32 *__restrict__ pw = sord + wb;
+        const u32 *__restrict__ pi = sidx + wb;
+        const u32 cnt = P.cnt, ca = cnt & 0xFFFFu, cb = cnt >> 16;
+        u32 ln = lane;
+        asm volatile("" : "+v"(ln));
+        if (ca) {
+            const u64 abase = cursor + P.base_a;
+            const bool fits = abase + ca <= a.k;   // else a round that misses: clip at k
+            u32 *__restrict__ oi = a.out_idx + abase;
+            u32 ra = 0;
+            static_for<COLS>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                const bool ia = (((j < 32) ? A0 : A1) >> (31 - (j & 31))) & 1u;
+                const u64 ma = ballot(ia);
+                if (ma) {
+                    if (ia) {
+                        const u32 q = mbcnt_add(ma, ra);
+                        if (fits || abase + q < a.k) {
+                            const u32 ie = KIND == 2 ? pi[j * WAVE + ln] : (u32)wb + (u32)(j * WAVE) + ln;
+                            oi[q] = ie;
+                            if (wkeys) a.out_keys[abase + q] = KIND == 2 ? a.keys[ie] : pw[j * WAVE + ln];
+                        }
+                    }
+                    ra += (u32)__popcll(ma);
+                }
+            });
+        }
+        if (cb == 0) {
+        } else if (cb <= (u32)SW_STASH) {
+            // b from the stash: contiguous, coalesced writes
+            const u64 pb0 = P.base_b;
+            for (u32 q0 = 0; q0 < cb; q0 += WAVE) {
+                const u32 q = q0 + ln;
+                const bool have = q < cb;
+                const u64 e = have ? P.stash[q] : 0ull;
+                const u32 o = ord_of<KIND, LARGEST>((u32)(e >> 32)), iv = (u32)e;
+                const u64 dst = pb0 + q;
+                if (have && dst < a.band_cap) {
+                    dord[dst] = o;
+                    didx[dst] = iv;
+                }
+                sample_append(a, st, have && hash_taken(a.seed, tag + 1, iv, hs_T), pack(o, iv));
+            }
+        } else {
+            // b did not fit the stash: read the wave-tile again, one column at a time
+            u64 pb = P.base_b;
+#pragma unroll 1
+            for (u32 j = 0; j < (u32)COLS; ++j) {
+                const u32 e = j * WAVE + ln;
+                const bool ok = wb + e < (u64)n;
+                const u32 xv = ok ? pw[e] : 0u;
+                const u32 iv = KIND == 2 ? (ok ? pi[e] : 0u) : (u32)wb + e;
+                bool ia, ic;
+                classify<KIND, LARGEST, FAST, true>(xv, iv, p, ia, ic);
+                const bool ibb = ok && !(ia || ic);
+                const u64 mb = ballot(ibb);
+                if (mb) {
+                    const u32 o = ord_of<KIND, LARGEST>(xv);
+                    const u64 q = pb + mbcnt(mb);
+                    if (ibb && q < a.band_cap) {
+                        dord[q] = o;
+                        didx[q] = iv;
+                    }
+                    sample_append(a, st, ibb && hash_taken(a.seed, tag + 1, iv, hs_T), pack(o, iv));
+                    pb += (u64)__popcll(mb);
+                }
+            }
+        }
+        if (lane == 0) lds_release(&P.state, 0u);
     };
 
     u32 cur = blockIdx.x * (u32)SW_DW + dw;
     if (cur < nwt) issue(cur);
+    u32 pa0 = 0, pa1 = 0, prev = 0;
     bool have_prev = false;
-    u32 prev = 0;
     for (u32 it = 0;; ++it) {
-        if (cur < nwt) {
-            // pass 1
-            WSlot &S = sh.slot[dw][it & 1u];
-            const u64 wb = (u64)cur * WSPAN;
-            const int rem = (u64)n - wb < WSPAN ? (int)((u64)n - wb) : (int)WSPAN;
-            const u32 ib = (u32)wb;
-            u32 ln = lane;
-            asm volatile("" : "+v"(ln));
-            u32 m0 = 0, m1 = 0, m2 = 0, m3 = 0, ta = 0, tb = 0;
-#pragma unroll
-            for (int j = 0; j < COLS; ++j) {
-                const u32 ie = KIND == 2 ? ix[j] : ib + (u32)(j * WAVE) + ln;
-                u64 mbl, mab;
-                classify<KIND, LARGEST, FAST>(x[j], ie, p, mbl, mab);
-                const u64 mv = ballot((int)ln < rem - j * WAVE);
-                const u64 ma = mbl & mv, mb = ~mbl & ~mab & mv;
-                if (ln == (u32)j) {
-                    m0 = (u32)ma; m1 = (u32)(ma >> 32);
-                    m2 = (u32)mb; m3 = (u32)(mb >> 32);
-                }
-                if (mb) {
-                    if ((mb >> ln) & 1ull) {
-                        const u32 q = tb + mbcnt(mb);
-                        if (q < (u32)SW_STASH) {
-                            const u32 o = KIND == 0 ? key_ord<true, LARGEST>(x[j])
-                                        : KIND == 1 ? (LARGEST ? ~x[j] : x[j]) : x[j];
-                            S.stash[q] = pack(o, ie);
-                        }
-                    }
-                }
-                ta += (u32)__popcll(ma);
-                tb += (u32)__popcll(mb);
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            *(uint4 *)&S.mask[ln][0] = make_uint4(m0, m1, m2, m3);
-            if (lane == 0) {
-                S.cnt = ta | (tb << 16);
-                lds_release(&S.state, 1u);
-            }
-        }
-        if (have_prev) {
-            // pass 2 of the previous wave-tile
-            WSlot &P = sh.slot[dw][(it - 1) & 1u];
-            while (lds_acquire(&P.state) != 2u) __builtin_amdgcn_s_sleep(1);
-            const u64 wb = (u64)prev * WSPAN;
-            const u32 *__restrict__ pw = sord + wb;
-            const u32 *__restrict__ pi = sidx + wb;
-            const u32 cb = P.cnt >> 16;
-            u64 pa = cursor + P.base_a;
-            const u64 pb0 = P.base_b;
-            u32 ln = lane;
-            asm volatile("" : "+v"(ln));
-            const uint4 mm = *(const uint4 *)&P.mask[ln][0];
-            const bool stashed = cb <= (u32)SW_STASH;
-            u64 pb = pb0;
-#pragma unroll
-            for (int j = 0; j < COLS; ++j) {
-                const u64 ma = ((u64)(u32)__builtin_amdgcn_readlane(mm.y, j) << 32) |
-                               (u32)__builtin_amdgcn_readlane(mm.x, j);
-                const u64 mb = stashed ? 0ull
-                             : ((u64)(u32)__builtin_amdgcn_readlane(mm.w, j) << 32) |
-                               (u32)__builtin_amdgcn_readlane(mm.z, j);
-                if (ma | mb) {
-                    const bool ia = (ma >> ln) & 1ull, ibm = (mb >> ln) & 1ull;
-                    // values not kept in LDS are read again (this wave-tile was just loaded)
-                    const bool need = ibm || (ia && (KIND == 2 || wkeys));
-                    u32 xv = 0, iv = 0;
-                    if (need) {
-                        xv = pw[j * WAVE + ln];
-                        if (KIND == 2) iv = pi[j * WAVE + ln];
-                    }
-                    const u32 ie = KIND == 2 ? iv : (u32)wb + (u32)(j * WAVE) + ln;
-                    if (ia) {
-                        const u64 q = pa + mbcnt(ma);
-                        if (q < a.k) {
-                            a.out_idx[q] = ie;
-                            if (wkeys) a.out_keys[q] = KIND == 2 ? a.keys[ie] : xv;
-                        }
-                    }
-                    if (ibm) {
-                        // b overflowed the LDS stash: write it from the data directly
-                        const u32 o = KIND == 0 ? key_ord<true, LARGEST>(xv)
-                                    : KIND == 1 ? (LARGEST ? ~xv : xv) : xv;
-                        const u64 q = pb + mbcnt(mb);
-                        if (q < a.band_cap) {
-                            dord[q] = o;
-                            didx[q] = ie;
-                        }
-                    }
-                    if (mb) {
-                        const u32 o = KIND == 0 ? key_ord<true, LARGEST>(xv)
-                                    : KIND == 1 ? (LARGEST ? ~xv : xv) : xv;
-                        sample_append(a, st, ibm && hash_taken(a.seed, tag + 1, ie, hs_T), pack(o, ie));
-                    }
-                    pa += (u64)__popcll(ma);
-                    pb += (u64)__popcll(mb);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            if (stashed) {
-                // b from the stash: contiguous, coalesced writes
-                for (u32 q0 = 0; q0 < cb; q0 += WAVE) {
-                    const u32 q = q0 + ln;
-                    const bool have = q < cb;
-                    const u64 e = have ? P.stash[q] : 0ull;
-                    const u64 dst = pb0 + q;
-                    if (have && dst < a.band_cap) {
-                        dord[dst] = (u32)(e >> 32);
-                        didx[dst] = (u32)e;
-                    }
-                    sample_append(a, st, have && hash_taken(a.seed, tag + 1, (u32)e, hs_T), e);
-                }
-            }
-            if (lane == 0) lds_release(&P.state, 0u);
-        }
+        u32 ca0 = 0, ca1 = 0;
+        if (cur < nwt) count_tile(cur, sh.slot[dw][it & 1u], ca0, ca1);
+        if (have_prev) write_tile(prev, sh.slot[dw][(it - 1) & 1u], pa0, pa1);
         if (cur >= nwt) break;
         const u32 nxt = cur + stride;
         if (nxt < nwt) issue(nxt);
         have_prev = true;
         prev = cur;
+        pa0 = ca0;
+        pa1 = ca1;
         cur = nxt;
     }
-    if (lane == 0)
-        __hip_atomic_fetch_add(&sh.done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // FIRST only names the instance enqueued for the first round (which reads
