@@ -829,32 +829,37 @@ __device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const P
         return tb;
     };
 
-    // Pass 1 with ties broken by position, reading the wave-tile again one
-    // column at a time (wave-tiles with a key equal to a pivot, and the last).
+    // Pass 1 with ties broken by position, over the wave-tile still in x[]
+    // (wave-tiles whose b holds a key equal to a pivot, and the last one).
     auto pass1_ties = [&](WSlot &S, u64 wb, u32 &A0, u32 &A1) -> u32 {
-        const u32 *__restrict__ pw = sord + wb;
-        const u32 *__restrict__ pi = sidx + wb;
+        u32 ln = lane;
+        asm volatile("" : "+v"(ln));
+        const int rem = (u64)n - wb < WSPAN ? (int)((u64)n - wb) : (int)WSPAN;
         u32 a0 = 0, a1 = 0, tb = 0;
-#pragma unroll 1
-        for (u32 j = 0; j < (u32)COLS; ++j) {
-            const u32 e = j * WAVE + lane;
-            const bool ok = wb + e < (u64)n;
-            const u32 xv = ok ? pw[e] : 0u;
-            const u32 iv = KIND == 2 ? (ok ? pi[e] : 0u) : (u32)wb + e;
+        static_for<COLS>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            const u32 ie = KIND == 2 ? ix[j] : (u32)wb + (u32)(j * WAVE) + ln;
+            const bool ok = (int)ln < rem - j * WAVE;
             bool ia, ic;
-            classify<KIND, LARGEST, FAST, true>(xv, iv, p, ia, ic);
+            classify<KIND, LARGEST, FAST, true>(x[j], ie, p, ia, ic);
             ia = ia && ok;
             ic = ic || !ok;
             if (j < 32) a0 = a0 + a0 + (u32)ia;
             else        a1 = a1 + a1 + (u32)ia;
+            asm volatile("" : "+v"(a0), "+v"(a1));
             const bool ibb = !(ia || ic);
             const u64 mb = ballot(ibb);
             if (mb) {
-                if (tb < (u32)SW_STASH && ibb) S.stash[mbcnt_add(mb, tb)] = pack(xv, iv);
+                if (tb < (u32)SW_STASH && ibb) {
+                    u32 xk = x[j];
+                    asm volatile("" : "+v"(xk));
+                    S.stash[mbcnt_add(mb, tb)] = pack(xk, ie);
+                }
                 tb += (u32)__popcll(mb);
             }
-        }
-        if (COLS <= 32) a1 = 0;
+            asm volatile("" : "+s"(tb));
+            __builtin_amdgcn_sched_barrier(0);
+        });
         A0 = a0;
         A1 = a1;
         return tb;
@@ -900,22 +905,59 @@ __device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const P
             const bool fits = abase + ca <= a.k;   // else a round that misses: clip at k
             u32 *__restrict__ oi = a.out_idx + abase;
             u32 ra = 0;
-            static_for<COLS>([&](auto jc) {
-                constexpr int j = decltype(jc)::value;
-                const bool ia = (((j < 32) ? A0 : A1) >> (31 - (j & 31))) & 1u;
-                const u64 ma = ballot(ia);
-                if (ma) {
-                    if (ia) {
-                        const u32 q = mbcnt_add(ma, ra);
-                        if (fits || abase + q < a.k) {
-                            const u32 ie = KIND == 2 ? pi[j * WAVE + ln] : (u32)wb + (u32)(j * WAVE) + ln;
-                            oi[q] = ie;
-                            if (wkeys) a.out_keys[abase + q] = KIND == 2 ? a.keys[ie] : pw[j * WAVE + ln];
+            auto abit = [&](int j) -> bool { return ((((j < 32) ? A0 : A1) >> (31 - (j & 31))) & 1u) != 0; };
+            if (KIND != 2 && !wkeys) {
+                // positions only: nothing to read
+                static_for<COLS>([&](auto jc) {
+                    constexpr int j = decltype(jc)::value;
+                    const bool ia = abit(j);
+                    const u64 ma = ballot(ia);
+                    if (ma) {
+                        if (ia) {
+                            const u32 q = mbcnt_add(ma, ra);
+                            if (fits || abase + q < a.k) oi[q] = (u32)wb + (u32)(j * WAVE) + ln;
                         }
+                        ra += (u32)__popcll(ma);
                     }
-                    ra += (u32)__popcll(ma);
-                }
-            });
+                });
+            } else {
+                // band positions (and keys) are read again: per group of
+                // columns all loads first, then one wait
+                constexpr int G = KIND == 2 ? 8 : 16;
+                static_for<COLS / G>([&](auto gc) {
+                    constexpr int g = decltype(gc)::value;
+                    u32 v[G], kv[G];
+                    static_for<G>([&](auto uc) {
+                        constexpr int u = decltype(uc)::value, j = g * G + u;
+                        v[u] = 0u;
+                        if (abit(j)) v[u] = KIND == 2 ? pi[j * WAVE + ln] : pw[j * WAVE + ln];
+                    });
+                    if (KIND == 2 && wkeys) {
+                        static_for<G>([&](auto uc) {
+                            constexpr int u = decltype(uc)::value, j = g * G + u;
+                            kv[u] = 0u;
+                            if (abit(j)) kv[u] = a.keys[v[u]];
+                        });
+                    }
+                    static_for<G>([&](auto uc) {
+                        constexpr int u = decltype(uc)::value, j = g * G + u;
+                        const bool ia = abit(j);
+                        const u64 ma = ballot(ia);
+                        if (ma) {
+                            if (ia) {
+                                const u32 q = mbcnt_add(ma, ra);
+                                if (fits || abase + q < a.k) {
+                                    const u32 ie = KIND == 2 ? v[u] : (u32)wb + (u32)(j * WAVE) + ln;
+                                    oi[q] = ie;
+                                    if (wkeys) a.out_keys[abase + q] = KIND == 2 ? kv[u] : v[u];
+                                }
+                            }
+                            ra += (u32)__popcll(ma);
+                        }
+                    });
+                    __builtin_amdgcn_sched_barrier(0);
+                });
+            }
         }
         if (cb == 0) {
         } else if (cb <= (u32)SW_STASH) {
@@ -971,6 +1013,7 @@ __device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const P
         if (have_prev) write_tile(prev, sh.slot[dw][(it - 1) & 1u], pa0, pa1);
         if (cur >= nwt) break;
         const u32 nxt = cur + stride;
+        asm volatile("" ::: "memory");   // the next loads stay after pass 2 (register budget)
         if (nxt < nwt) issue(nxt);
         have_prev = true;
         prev = cur;
