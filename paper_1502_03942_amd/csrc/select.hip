@@ -28,8 +28,14 @@ namespace topk {
 
 typedef u32 u32x4 __attribute__((ext_vector_type(4)));
 
+constexpr int RS_BITS = 12;                    // radix select digit
+constexpr u32 RS_BINS = 1u << RS_BITS;
 struct Smem {
-    u32 hist[2][256];
+    u32 rhist[2][RS_BINS];
+    u64 rmin[2], rmax[2];
+    u64 cand[2][WAVE];
+    u32 ccount[2];
+    u32 rscan[2][8];
     u32 scan[PV_THREADS / WAVE];
     u32 sel_bin[2], sel_before[2], sel_count[2];
     u64 found[2];
@@ -42,91 +48,154 @@ struct Smem {
 // ---------------------------------------------------------------------------
 // Radix select in one workgroup.  Every thread holds up to M keys in registers
 // (the first `cnt` valid).  Finds the keys of 0-based ranks rank[0] and rank[1]
-// (each only if act[t]) among all valid keys, most significant byte first:
-// histogram the next byte of the keys that share the prefix found so far,
-// locate the byte that holds the rank, narrow, stop as soon as a bucket holds
-// one key.  Keys must be distinct (they are (ord, position) pairs).
+// (each only if act[t]) among all valid keys.  Keys must be distinct (they are
+// (ord, position) pairs).
+//
+// The candidates of a target are the keys that share the bits fixed so far.
+// A pass takes their minimum and maximum, histograms the RS_BITS bits just
+// below the common prefix of the two (so bits every candidate shares cost no
+// pass) and keeps the bucket that holds the rank.  Once that bucket holds at
+// most 64 keys they are gathered and one wave ranks them directly.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void hist_add(u32 *h, int d)
+__device__ __forceinline__ bool rs_match(u64 x, u64 pref, int lowb)
 {
-    const u64 act = ballot(d >= 0);
-    if (act == 0) return;
-    const int fl = __ffsll((unsigned long long)act) - 1;
-    const int dl = __shfl(d, fl, WAVE);
-    const u64 same = ballot(d == dl);
-    if ((int)lane_id() == fl) atomicAdd(&h[dl], (u32)__popcll(same));
-    if (d >= 0 && d != dl) atomicAdd(&h[d], 1u);
+    return lowb >= 64 || (x >> lowb) == (pref >> lowb);
 }
 
 template <int M>
 __device__ __forceinline__ void radix_select(const u64 (&v)[M], int cnt, const u64 rank_in[2],
-                             const bool act[2], u64 out[2], Smem &sm)
+                                             const bool act[2], u64 out[2], Smem &sm)
 {
-    const u32 tid = threadIdx.x;
-    u64 prefix[2] = {0ull, 0ull};
+    const u32 tid = threadIdx.x, lane = lane_id();
+    const u32 w = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    u64 pref[2] = {0ull, 0ull};
+    int lowb[2] = {64, 64};               // bits [lowb, 64) of the candidates equal pref's
     u64 rank[2] = {rank_in[0], rank_in[1]};
-    bool uniq[2] = {false, false};
-    int ushift[2] = {0, 0};
-    for (int shift = 56; shift >= 0; shift -= 8) {
-        const bool need0 = act[0] && !uniq[0];
-        const bool need1 = act[1] && !uniq[1];
-        if (!need0 && !need1) break;
-        for (u32 i = tid; i < 512; i += PV_THREADS) (&sm.hist[0][0])[i] = 0u;
-        __syncthreads();
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            if (t == 0 ? need0 : need1) {
-#pragma unroll
-                for (int j = 0; j < M; ++j) {
-                    const bool m = j < cnt &&
-                        (shift == 56 || ((v[j] ^ prefix[t]) >> (shift + 8)) == 0);
-                    const int d = m ? (int)((v[j] >> shift) & 255u) : -1;
-                    hist_add(sm.hist[t], d);
-                }
-            }
-        }
-        __syncthreads();
-        const u32 w = tid / WAVE;
-        if (w < 2 && (w == 0 ? need0 : need1)) {
-            const u32 l = lane_id();
-            const u32 c0 = sm.hist[w][4 * l], c1 = sm.hist[w][4 * l + 1];
-            const u32 c2 = sm.hist[w][4 * l + 2], c3 = sm.hist[w][4 * l + 3];
-            const u32 tot = c0 + c1 + c2 + c3;
-            u64 before = wave_incl_scan(tot) - tot;
-            const u64 r = rank[w];
-            const u32 c[4] = {c0, c1, c2, c3};
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                if (before <= r && r < before + c[b]) {
-                    sm.sel_bin[w] = 4 * l + b;
-                    sm.sel_before[w] = (u32)before;
-                    sm.sel_count[w] = c[b];
-                }
-                before += c[b];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            if (t == 0 ? need0 : need1) {
-                prefix[t] |= (u64)sm.sel_bin[t] << shift;
-                rank[t] -= sm.sel_before[t];
-                if (sm.sel_count[t] == 1u) { uniq[t] = true; ushift[t] = shift; }
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        if (act[t]) {
-#pragma unroll
-            for (int j = 0; j < M; ++j)
-                if (j < cnt && ((v[j] ^ prefix[t]) >> ushift[t]) == 0) sm.found[t] = v[j];
-        }
+    bool done[2] = {!act[0], !act[1]};
+    u64 res[2] = {0ull, 0ull};
+    for (u32 i = tid; i < 2u * RS_BINS; i += PV_THREADS) (&sm.rhist[0][0])[i] = 0u;
+    if (tid < 2) {
+        sm.rmin[tid] = ~0ull;
+        sm.rmax[tid] = 0ull;
+        sm.ccount[tid] = 0u;
     }
     __syncthreads();
-    out[0] = sm.found[0];
-    out[1] = sm.found[1];
+    for (int pass = 0; pass < 8 && !(done[0] && done[1]); ++pass) {
+        // (1) minimum and maximum of each target's candidates
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            if (done[t]) continue;
+            u64 mn = ~0ull, mx = 0ull;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                if (j < cnt && rs_match(v[j], pref[t], lowb[t])) {
+                    mn = v[j] < mn ? v[j] : mn;
+                    mx = v[j] > mx ? v[j] : mx;
+                }
+            }
+            mn = wave_min_u64(mn);
+            mx = wave_max_u64(mx);
+            if (lane == 0 && mn <= mx) {
+                atomicMin((unsigned long long *)&sm.rmin[t], (unsigned long long)mn);
+                atomicMax((unsigned long long *)&sm.rmax[t], (unsigned long long)mx);
+            }
+        }
+        __syncthreads();
+        // (2) histogram of the window below the common prefix
+        int sh[2] = {0, 0};
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            if (done[t]) continue;
+            const u64 mn = sm.rmin[t], mx = sm.rmax[t];
+            if (mn == mx) {
+                res[t] = mn;
+                done[t] = true;
+                continue;
+            }
+            const int hb = 63 - __clzll((long long)(mn ^ mx));
+            sh[t] = hb >= RS_BITS - 1 ? hb - (RS_BITS - 1) : 0;
+#pragma unroll
+            for (int j = 0; j < M; ++j)
+                if (j < cnt && rs_match(v[j], pref[t], lowb[t]))
+                    atomicAdd(&sm.rhist[t][(u32)(v[j] >> sh[t]) & (RS_BINS - 1)], 1u);
+        }
+        __syncthreads();
+        // (3) scan: waves 8t .. 8t+7 cover target t's bins, lane l eight of them
+        const u32 t3 = w >> 3, sw = w & 7u;
+        const u32 b0 = sw * (RS_BINS / 8) + lane * 8u;
+        u32 c[8], csum = 0, cincl = 0;
+        if (!done[t3]) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                c[i] = sm.rhist[t3][b0 + i];
+                csum += c[i];
+            }
+            cincl = wave_incl_scan(csum);
+            if (lane == WAVE - 1) sm.rscan[t3][sw] = cincl;
+        }
+        __syncthreads();
+        if (!done[t3]) {
+            u32 before = cincl - csum;
+            for (u32 i = 0; i < sw; ++i) before += sm.rscan[t3][i];
+            const u64 r = rank[t3];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                if ((u64)before <= r && r < (u64)before + c[i]) {
+                    sm.sel_bin[t3] = b0 + (u32)i;
+                    sm.sel_before[t3] = before;
+                    sm.sel_count[t3] = c[i];
+                }
+                before += c[i];
+                sm.rhist[t3][b0 + i] = 0u;       // clean for the next pass
+            }
+        }
+        __syncthreads();
+        // (4) narrow to the bucket; gather it when small
+        bool gather[2] = {false, false};
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            if (done[t]) continue;
+            const u64 mn = sm.rmin[t];
+            const int top = sh[t] + RS_BITS;
+            const u64 high = top >= 64 ? 0ull : (mn >> top) << top;
+            pref[t] = high | ((u64)sm.sel_bin[t] << sh[t]);
+            lowb[t] = sh[t];
+            rank[t] -= sm.sel_before[t];
+            gather[t] = sm.sel_count[t] <= (u32)WAVE;
+        }
+        __syncthreads();
+        if (tid < 2) {
+            sm.rmin[tid] = ~0ull;
+            sm.rmax[tid] = 0ull;
+        }
+        if (gather[0] || gather[1]) {
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                if (!gather[t]) continue;
+#pragma unroll
+                for (int j = 0; j < M; ++j)
+                    if (j < cnt && rs_match(v[j], pref[t], lowb[t]))
+                        sm.cand[t][atomicAdd(&sm.ccount[t], 1u)] = v[j];
+            }
+            __syncthreads();
+            if (w < 2 && gather[w]) {
+                const u32 m = sm.ccount[w];
+                const u64 mine = lane < m ? sm.cand[w][lane] : ~0ull;
+                u32 below = 0;
+                for (u32 i = 0; i < m; ++i) below += sm.cand[w][i] < mine ? 1u : 0u;
+                if (lane < m && (u64)below == rank[w]) sm.found[w] = mine;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                if (!gather[t]) continue;
+                res[t] = sm.found[t];
+                done[t] = true;
+            }
+        }
+    }
+    out[0] = res[0];
+    out[1] = res[1];
     __syncthreads();
 }
 
@@ -891,7 +960,8 @@ __device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const P
         }
     };
 
-    // Pass 2: write a and b of a counted wave-tile (its loads are gone).
+    // Pass 2: write a and b of a counted wave-tile.  Band input runs it right
+    // after pass 1 (positions still in ix[]); key input one wave-tile later.
     auto write_tile = [&](u32 wt, WSlot &P, u32 A0, u32 A1) {
         while (lds_acquire(&P.state) != 2u) __builtin_amdgcn_s_sleep(1);
         const u64 wb = (u64)wt * WSPAN;
@@ -906,8 +976,8 @@ __device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const P
             u32 *__restrict__ oi = a.out_idx + abase;
             u32 ra = 0;
             auto abit = [&](int j) -> bool { return ((((j < 32) ? A0 : A1) >> (31 - (j & 31))) & 1u) != 0; };
-            if (KIND != 2 && !wkeys) {
-                // positions only: nothing to read
+            if (!wkeys) {
+                // positions only (band input: still in registers)
                 static_for<COLS>([&](auto jc) {
                     constexpr int j = decltype(jc)::value;
                     const bool ia = abit(j);
@@ -915,30 +985,24 @@ __device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const P
                     if (ma) {
                         if (ia) {
                             const u32 q = mbcnt_add(ma, ra);
-                            if (fits || abase + q < a.k) oi[q] = (u32)wb + (u32)(j * WAVE) + ln;
+                            if (fits || abase + q < a.k)
+                                oi[q] = KIND == 2 ? ix[j] : (u32)wb + (u32)(j * WAVE) + ln;
                         }
                         ra += (u32)__popcll(ma);
                     }
                 });
             } else {
-                // band positions (and keys) are read again: per group of
-                // columns all loads first, then one wait
-                constexpr int G = KIND == 2 ? 8 : 16;
+                // keys are read again: per group of columns all loads first,
+                // then one wait
+                constexpr int G = 16;
                 static_for<COLS / G>([&](auto gc) {
                     constexpr int g = decltype(gc)::value;
-                    u32 v[G], kv[G];
+                    u32 kv[G];
                     static_for<G>([&](auto uc) {
                         constexpr int u = decltype(uc)::value, j = g * G + u;
-                        v[u] = 0u;
-                        if (abit(j)) v[u] = KIND == 2 ? pi[j * WAVE + ln] : pw[j * WAVE + ln];
+                        kv[u] = 0u;
+                        if (abit(j)) kv[u] = KIND == 2 ? a.keys[ix[j]] : pw[j * WAVE + ln];
                     });
-                    if (KIND == 2 && wkeys) {
-                        static_for<G>([&](auto uc) {
-                            constexpr int u = decltype(uc)::value, j = g * G + u;
-                            kv[u] = 0u;
-                            if (abit(j)) kv[u] = a.keys[v[u]];
-                        });
-                    }
                     static_for<G>([&](auto uc) {
                         constexpr int u = decltype(uc)::value, j = g * G + u;
                         const bool ia = abit(j);
@@ -947,9 +1011,8 @@ __device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const P
                             if (ia) {
                                 const u32 q = mbcnt_add(ma, ra);
                                 if (fits || abase + q < a.k) {
-                                    const u32 ie = KIND == 2 ? v[u] : (u32)wb + (u32)(j * WAVE) + ln;
-                                    oi[q] = ie;
-                                    if (wkeys) a.out_keys[abase + q] = KIND == 2 ? kv[u] : v[u];
+                                    oi[q] = KIND == 2 ? ix[j] : (u32)wb + (u32)(j * WAVE) + ln;
+                                    a.out_keys[abase + q] = kv[u];
                                 }
                             }
                             ra += (u32)__popcll(ma);
@@ -1009,6 +1072,16 @@ __device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const P
     bool have_prev = false;
     for (u32 it = 0;; ++it) {
         u32 ca0 = 0, ca1 = 0;
+        if (KIND == 2) {
+            // band input: the reservation wait is exposed, band positions need no reload
+            if (cur >= nwt) break;
+            count_tile(cur, sh.slot[dw][it & 1u], ca0, ca1);
+            write_tile(cur, sh.slot[dw][it & 1u], ca0, ca1);
+            cur += stride;
+            asm volatile("" ::: "memory");
+            if (cur < nwt) issue(cur);
+            continue;
+        }
         if (cur < nwt) count_tile(cur, sh.slot[dw][it & 1u], ca0, ca1);
         if (have_prev) write_tile(prev, sh.slot[dw][(it - 1) & 1u], pa0, pa1);
         if (cur >= nwt) break;
