@@ -30,7 +30,7 @@ constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t x, size_t a = ALIGN) { return (x + a - 1) / a * a; }
 
 struct Layout {
-    size_t state, hs, band[4], trace, total;
+    size_t state, hs, seg, band[4], trace, total;
     uint32_t band_cap, band_alloc;
 };
 
@@ -42,6 +42,8 @@ Layout make_layout(const topk_ctx *c, uint64_t n, uint32_t flags)
     off = align_up(off + sizeof(State));
     L.hs = off;
     off = align_up(off + (size_t)S_MAX * sizeof(uint64_t));
+    L.seg = off;
+    off = align_up(off + (size_t)NSEG * sizeof(uint32_t));
     uint64_t cap = n / (uint64_t)c->band_div + 65536;
     if (cap > n) cap = n;
     if (n <= (uint64_t)c->t_fin) cap = 0;
@@ -124,6 +126,7 @@ int select_common(topk_ctx *c, const K *keys, uint64_t n, uint64_t k, uint32_t f
     a.status = status;
     a.st = (State *)(w + L.state);
     a.hs_buf = (uint64_t *)(w + L.hs);
+    a.seg_cnt = (uint32_t *)(w + L.seg);
     a.band_cap = L.band_cap;
     a.band_ord[0] = (uint32_t *)(w + L.band[0]);
     a.band_idx[0] = (uint32_t *)(w + L.band[1]);

@@ -1,6 +1,7 @@
 // Device-side building blocks shared by the selection kernels (gfx950, wave64).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <stdint.h>
 
 namespace topk {
@@ -66,44 +67,62 @@ __device__ __forceinline__ u32 mbcnt(u64 mask)
 
 __device__ __forceinline__ u64 ballot(bool p) { return __ballot(p); }
 
-__device__ __forceinline__ u32 wave_sum_u32(u32 v)
+// Cross-lane steps on the DPP network (row = 16 lanes): no LDS round trip.
+// dpp<CTRL, ROWS>(v): v from the lane CTRL names, 0 where there is none or
+// the destination row is not in ROWS.
+enum : int {
+    DPP_XOR1 = 0xB1,            // quad_perm [1,0,3,2]
+    DPP_XOR2 = 0x4E,            // quad_perm [2,3,0,1]
+    DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118,
+    DPP_ROW_MIRROR = 0x140, DPP_ROW_HALF_MIRROR = 0x141,
+    DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143,
+};
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ u32 dpp(u32 v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-    return v;
-}
-
-__device__ __forceinline__ u64 wave_max_u64(u64 v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        u64 w = __shfl_xor(v, o, WAVE);
-        v = w > v ? w : v;
-    }
-    return v;
-}
-
-__device__ __forceinline__ u64 wave_min_u64(u64 v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        u64 w = __shfl_xor(v, o, WAVE);
-        v = w < v ? w : v;
-    }
-    return v;
+    return (u32)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, true);
 }
 
 // inclusive prefix sum across the wave
 __device__ __forceinline__ u32 wave_incl_scan(u32 v)
 {
-    const u32 l = lane_id();
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        u32 w = __shfl_up(v, o, WAVE);
-        if (l >= (u32)o) v += w;
-    }
+    v += dpp<DPP_ROW_SHR1>(v);
+    v += dpp<DPP_ROW_SHR2>(v);
+    v += dpp<DPP_ROW_SHR4>(v);
+    v += dpp<DPP_ROW_SHR8>(v);
+    v += dpp<DPP_ROW_BCAST15, 0xA>(v);
+    v += dpp<DPP_ROW_BCAST31, 0xC>(v);
     return v;
 }
+
+__device__ __forceinline__ u32 wave_sum_u32(u32 v)
+{
+    return (u32)__builtin_amdgcn_readlane((int)wave_incl_scan(v), WAVE - 1);
+}
+
+// min / max over the wave (wave-uniform result)
+template <bool MAX>
+__device__ __forceinline__ u64 wave_ext_u64(u64 v)
+{
+    auto step = [&](auto ctrl_tag, auto rows_tag) {
+        constexpr int C = decltype(ctrl_tag)::value, R = decltype(rows_tag)::value;
+        const u32 lo = (u32)__builtin_amdgcn_update_dpp((int)(u32)v, (int)(u32)v, C, R, 0xF, false);
+        const u32 hi = (u32)__builtin_amdgcn_update_dpp((int)(u32)(v >> 32), (int)(u32)(v >> 32), C, R, 0xF, false);
+        const u64 w = ((u64)hi << 32) | lo;
+        v = MAX ? (w > v ? w : v) : (w < v ? w : v);
+    };
+    step(std::integral_constant<int, DPP_XOR1>(), std::integral_constant<int, 0xF>());
+    step(std::integral_constant<int, DPP_XOR2>(), std::integral_constant<int, 0xF>());
+    step(std::integral_constant<int, DPP_ROW_HALF_MIRROR>(), std::integral_constant<int, 0xF>());
+    step(std::integral_constant<int, DPP_ROW_MIRROR>(), std::integral_constant<int, 0xF>());
+    step(std::integral_constant<int, DPP_ROW_BCAST15>(), std::integral_constant<int, 0xA>());
+    step(std::integral_constant<int, DPP_ROW_BCAST31>(), std::integral_constant<int, 0xC>());
+    const u32 lo = (u32)__builtin_amdgcn_readlane((int)(u32)v, WAVE - 1);
+    const u32 hi = (u32)__builtin_amdgcn_readlane((int)(u32)(v >> 32), WAVE - 1);
+    return ((u64)hi << 32) | lo;
+}
+__device__ __forceinline__ u64 wave_max_u64(u64 v) { return wave_ext_u64<true>(v); }
+__device__ __forceinline__ u64 wave_min_u64(u64 v) { return wave_ext_u64<false>(v); }
 
 // Exclusive prefix sum over a workgroup of NT threads; returns this thread's
 // exclusive prefix and writes the total to *total.  `scratch` holds NT/64 u32.

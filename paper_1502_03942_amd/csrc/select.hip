@@ -68,6 +68,8 @@ __device__ __forceinline__ void radix_select(const u64 (&v)[M], int cnt, const u
 {
     const u32 tid = threadIdx.x, lane = lane_id();
     const u32 w = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    // slots at or past the wave's largest count hold nothing: skip them uniformly
+    const int cw = (int)wave_max_u64((u64)(cnt > 0 ? cnt : 0));
     u64 pref[2] = {0ull, 0ull};
     int lowb[2] = {64, 64};               // bits [lowb, 64) of the candidates equal pref's
     u64 rank[2] = {rank_in[0], rank_in[1]};
@@ -88,6 +90,7 @@ __device__ __forceinline__ void radix_select(const u64 (&v)[M], int cnt, const u
             u64 mn = ~0ull, mx = 0ull;
 #pragma unroll
             for (int j = 0; j < M; ++j) {
+                if (j >= cw) break;
                 if (j < cnt && rs_match(v[j], pref[t], lowb[t])) {
                     mn = v[j] < mn ? v[j] : mn;
                     mx = v[j] > mx ? v[j] : mx;
@@ -115,9 +118,11 @@ __device__ __forceinline__ void radix_select(const u64 (&v)[M], int cnt, const u
             const int hb = 63 - __clzll((long long)(mn ^ mx));
             sh[t] = hb >= RS_BITS - 1 ? hb - (RS_BITS - 1) : 0;
 #pragma unroll
-            for (int j = 0; j < M; ++j)
+            for (int j = 0; j < M; ++j) {
+                if (j >= cw) break;
                 if (j < cnt && rs_match(v[j], pref[t], lowb[t]))
                     atomicAdd(&sm.rhist[t][(u32)(v[j] >> sh[t]) & (RS_BINS - 1)], 1u);
+            }
         }
         __syncthreads();
         // (3) scan: waves 8t .. 8t+7 cover target t's bins, lane l eight of them
@@ -173,16 +178,23 @@ __device__ __forceinline__ void radix_select(const u64 (&v)[M], int cnt, const u
             for (int t = 0; t < 2; ++t) {
                 if (!gather[t]) continue;
 #pragma unroll
-                for (int j = 0; j < M; ++j)
+                for (int j = 0; j < M; ++j) {
+                    if (j >= cw) break;
                     if (j < cnt && rs_match(v[j], pref[t], lowb[t]))
                         sm.cand[t][atomicAdd(&sm.ccount[t], 1u)] = v[j];
+                }
             }
             __syncthreads();
             if (w < 2 && gather[w]) {
                 const u32 m = sm.ccount[w];
                 const u64 mine = lane < m ? sm.cand[w][lane] : ~0ull;
+                const u32 mlo = (u32)mine, mhi = (u32)(mine >> 32);
                 u32 below = 0;
-                for (u32 i = 0; i < m; ++i) below += sm.cand[w][i] < mine ? 1u : 0u;
+                for (u32 i = 0; i < m; ++i) {
+                    const u64 o = ((u64)(u32)__builtin_amdgcn_readlane((int)mhi, (int)i) << 32) |
+                                  (u32)__builtin_amdgcn_readlane((int)mlo, (int)i);
+                    below += o < mine ? 1u : 0u;
+                }
                 if (lane < m && (u64)below == rank[w]) sm.found[w] = mine;
             }
             __syncthreads();
@@ -347,16 +359,98 @@ __device__ __forceinline__ u64 fetch_elem(const SelArgs &a, u32 src, u64 p)
 // 1 + floor(ln U / ln(1 - rho)), U from Philox4x32-10 counter
 // (draw/4, t, attempt, 0) and key = seed; it keeps at most SEG_CAP positions.
 // ---------------------------------------------------------------------------
+// Geometric-skip Bernoulli sampler of one segment (§2 sampling; each of the
+// n positions is taken independently with probability rho = s_target / n).
+// Segment t of NSEG covers [t L, min(t L + L, n)), L = ceil(n / NSEG); skip
+// j of the segment is 1 + floor(ln U / ln(1 - rho)) with U = (w + 1/2) 2^-32,
+// w the word j % 4 of Philox4x32-10 at counter (j / 4, t, tag, 0), key =
+// seed.  At most SEG_CAP positions per segment.  Returns their count.
+__device__ __forceinline__ int skip_sample(u32 t, u32 n, u32 s_target, u64 seed, u32 tag,
+                                           u32 (&pos)[SEG_CAP])
+{
+    const double rho = (double)s_target / (double)n;
+    const u64 L = ((u64)n + NSEG - 1) / NSEG;
+    const u64 s0 = (u64)t * L;
+    const u64 e0 = s0 + L < (u64)n ? s0 + L : (u64)n;
+    int cnt = 0;
+    if (s0 >= e0) return 0;
+    if (rho >= 1.0) {
+#pragma unroll
+        for (int j = 0; j < SEG_CAP; ++j)
+            if (s0 + j < e0) { pos[j] = (u32)(s0 + j); cnt = j + 1; }
+        return cnt;
+    }
+    const double ln1mrho = log1p(-rho);
+    i64 p = (i64)s0 - 1;
+    bool stop = false;
+    uint4 r4 = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int j = 0; j < SEG_CAP; ++j) {
+        if (!stop) {
+            if ((j & 3) == 0)
+                r4 = philox4x32_10(make_uint4((u32)(j >> 2), t, tag, 0u), (u32)seed, (u32)(seed >> 32));
+            const u32 w = (j & 3) == 0 ? r4.x : (j & 3) == 1 ? r4.y : (j & 3) == 2 ? r4.z : r4.w;
+            const double u = ((double)w + 0.5) * (1.0 / 4294967296.0);
+            const double q = log(u) / ln1mrho;
+            if (q >= (double)((i64)e0 - 1 - p)) {
+                stop = true;
+            } else {
+                p = p + 1 + (i64)q;
+                pos[j] = (u32)p;
+                cnt = j + 1;
+            }
+        }
+    }
+    return cnt;
+}
+
+// Round 1's sample with one lane per (segment, skip): the skips of a segment
+// do not depend on each other, only their running sum does, so lane j of a
+// 16-lane row computes skip j (the same fp64 operations as skip_sample) and
+// a row prefix sum gives the positions.  A skip is clamped to L + 1, which
+// leaves every position past the segment's end past it.
+template <bool IS_F32, bool LARGEST>
+__global__ __launch_bounds__(WAVE) void k_sample(SelArgs a)
+{
+    static_assert(SEG_CAP == 16, "one DPP row per segment");
+    const u32 g = blockIdx.x * WAVE + threadIdx.x;
+    const u32 t = g / SEG_CAP, j = g % SEG_CAP;
+    const u32 n = a.n;
+    const double rho = (double)a.s_target / (double)n;
+    const u64 L = ((u64)n + NSEG - 1) / NSEG;
+    const u64 s0 = (u64)t * L;
+    const u64 e0 = s0 + L < (u64)n ? s0 + L : (u64)n;
+    u32 skip;
+    if (rho >= 1.0) {
+        skip = 1u;
+    } else {
+        const uint4 r4 = philox4x32_10(make_uint4(j >> 2, t, 0u, 0u), (u32)a.seed, (u32)(a.seed >> 32));
+        const u32 w = (j & 3) == 0 ? r4.x : (j & 3) == 1 ? r4.y : (j & 3) == 2 ? r4.z : r4.w;
+        const double u = ((double)w + 0.5) * (1.0 / 4294967296.0);
+        const double q = log(u) / log1p(-rho);
+        skip = q >= (double)L ? (u32)L + 1u : 1u + (u32)(u64)q;
+    }
+    // inclusive sum over the row (the segment)
+    u32 sum = skip;
+    sum += dpp<DPP_ROW_SHR1>(sum);
+    sum += dpp<DPP_ROW_SHR2>(sum);
+    sum += dpp<DPP_ROW_SHR4>(sum);
+    sum += dpp<DPP_ROW_SHR8>(sum);
+    const u64 p = s0 - 1 + (u64)sum;
+    const bool ok = s0 < e0 && p < e0;
+    if (ok) a.hs_buf[t * SEG_CAP + j] = fetch_elem<IS_F32, LARGEST>(a, 0u, (u32)p);
+    const u64 m = ballot(ok);
+    if (j == 0) a.seg_cnt[t] = (u32)__popcll(m & (0xFFFFull << (lane_id() & 48u)));
+}
+
 template <bool IS_F32, bool LARGEST>
 __device__ __forceinline__ void sample_and_pivot(const SelArgs &a, State *st, Smem &sm)
 {
     const u32 tid = threadIdx.x;
     const u32 n = sm.n_cur, k = sm.k_cur, src = sm.src, tag = sm.tag;
-    const double rho = (double)a.s_target / (double)n;
-    const u64 L = ((u64)n + NSEG - 1) / NSEG;
-    const u64 s0 = (u64)tid * L;
-    const u64 e0 = s0 + L < (u64)n ? s0 + L : (u64)n;
     const bool collected = sm.hs_ok != 0;   // sample drawn while this subproblem was formed
+    // round 1's sample drawn by k_sample (segment t in hs_buf[t SEG_CAP ..])
+    const bool pre = a.presampled && tag == 0 && src == 0;
     u32 pos[SEG_CAP];
     int cnt = 0;
     if (collected) {
@@ -364,42 +458,17 @@ __device__ __forceinline__ void sample_and_pivot(const SelArgs &a, State *st, Sm
 #pragma unroll
         for (int j = 0; j < SEG_CAP; ++j)
             if (tid + (u32)j * PV_THREADS < hc) cnt = j + 1;
-    } else if (s0 < e0) {
-        if (rho >= 1.0) {
-#pragma unroll
-            for (int j = 0; j < SEG_CAP; ++j)
-                if (s0 + j < e0) { pos[j] = (u32)(s0 + j); cnt = j + 1; }
-        } else {
-            const double ln1mrho = log1p(-rho);
-            i64 p = (i64)s0 - 1;
-            bool stop = false;
-            uint4 r4 = make_uint4(0u, 0u, 0u, 0u);
-#pragma unroll
-            for (int j = 0; j < SEG_CAP; ++j) {
-                if (!stop) {
-                    if ((j & 3) == 0)
-                        r4 = philox4x32_10(make_uint4((u32)(j >> 2), tid, tag, 0u),
-                                           (u32)a.seed, (u32)(a.seed >> 32));
-                    const u32 w = (j & 3) == 0 ? r4.x : (j & 3) == 1 ? r4.y
-                                : (j & 3) == 2 ? r4.z : r4.w;
-                    const double u = ((double)w + 0.5) * (1.0 / 4294967296.0);
-                    const double q = log(u) / ln1mrho;
-                    if (q >= (double)((i64)e0 - 1 - p)) {
-                        stop = true;
-                    } else {
-                        p = p + 1 + (i64)q;
-                        pos[j] = (u32)p;
-                        cnt = j + 1;
-                    }
-                }
-            }
-        }
+    } else if (pre) {
+        cnt = (int)a.seg_cnt[tid];
+    } else {
+        cnt = skip_sample(tid, n, a.s_target, a.seed, tag, pos);
     }
     u64 v[SEG_CAP];
 #pragma unroll
     for (int j = 0; j < SEG_CAP; ++j)
         v[j] = j >= cnt ? ~0ull
              : collected ? a.hs_buf[tid + (u32)j * PV_THREADS]
+             : pre ? a.hs_buf[tid * SEG_CAP + (u32)j]
              : fetch_elem<IS_F32, LARGEST>(a, src, pos[j]);
 
     u32 s_total;
@@ -408,7 +477,7 @@ __device__ __forceinline__ void sample_and_pivot(const SelArgs &a, State *st, Sm
         u32 *tp = a.trace_pos + (u64)tag * TRACE_STRIDE + excl;
 #pragma unroll
         for (int j = 0; j < SEG_CAP; ++j)
-            if (j < cnt) tp[j] = pos[j];
+            if (j < cnt) tp[j] = pre ? (u32)v[j] : pos[j];
     }
     if (tid == 0) {
         i64 lo, hi;
@@ -1144,6 +1213,8 @@ static hipError_t launch_impl(SelArgs a, const SelLaunch &L, hipStream_t s, Kern
         return hipGetLastError();
     }
     t = tm_begin(tm, KT_PIVOT_FIRST, s);
+    a.presampled = 1;
+    hipLaunchKernelGGL((k_sample<F, LG>), dim3(NSEG * SEG_CAP / WAVE), dim3(WAVE), 0, s, a);
     hipLaunchKernelGGL((k_pivot<F, LG>), dim3(1), dim3(PV_THREADS), 0, s, a);
     tm_end(tm, t, s);
     a.first = 0;

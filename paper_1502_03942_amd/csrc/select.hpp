@@ -51,9 +51,11 @@ struct SelArgs {
     uint32_t *band_ord[2], *band_idx[2];
     uint32_t *trace_pos;        // [R_TRACE][TRACE_STRIDE] or nullptr
     uint64_t *hs_buf;           // [S_MAX] sample drawn while b is formed: ord << 32 | position
+    uint32_t *seg_cnt;          // [NSEG] round 1's sample size per segment (k_sample)
     uint32_t s_target, c_num0, t_fin, r_max;
     uint64_t seed;
     uint32_t first;             // first kernel of the call: initialise the state
+    uint32_t presampled;        // round 1's sample is in hs_buf / seg_cnt
 };
 
 struct SelLaunch {
