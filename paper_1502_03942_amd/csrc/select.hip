@@ -290,6 +290,7 @@ __device__ __forceinline__ void state_init(const SelArgs &a, State *st)
     st->nrec = 0;
     st->hs_ok = 0;
     st->resv = 0;
+    st->gen = 0;
     st->hs_count = 0;
 }
 
@@ -517,6 +518,7 @@ __device__ __forceinline__ void sample_and_pivot(const SelArgs &a, State *st, Sm
         st->phase = PH_SWEEP;
         // the coming sweep reserves output space and draws the next sample
         st->resv = 0ull;
+        st->gen = 0u;
         st->hs_count = 0u;
         st->hs_T = band_threshold(n, s_total, lo, hi, a.s_target);
         sm.hs_T = st->hs_T;
@@ -838,8 +840,11 @@ struct WSlot {
     u32 base_a, base_b;         // reserved output positions (relative to the round's start)
     u32 state;                  // 0 free, 1 counted (posted), 2 space reserved
 };
+constexpr u32 SW_GRING = 4;     // generation numbers published ahead (ring)
 struct SwShared {
-    WSlot slot[SW_DW][2];       // [data wave][generation parity]
+    WSlot slot[SW_DW][SW_SLOTS];    // [data wave][generation % SW_SLOTS]
+    u32 gnum[SW_GRING];             // workgroup's generation t: wave-tiles gnum W + dw
+    u32 gseq[SW_GRING];             // t + 1 once gnum[t % SW_GRING] is published
 };
 
 __device__ __forceinline__ u32 lds_acquire(u32 *p)
@@ -866,18 +871,40 @@ __device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const P
     const u32 lane = lane_id();
     const u32 w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const u32 nwt = (u32)(((u64)n + WSPAN - 1) / WSPAN);
-    const u32 stride = gridDim.x * (u32)SW_DW;
 
     if (w == 0) {
         // ------------- control wave: one reservation per generation -------------
+        // Generation t of this workgroup is the generation number g_t: its
+        // wave-tiles are g_t W + dw (W = SW_DW).  g_0 = blockIdx; later ones
+        // come from a global counter (so faster workgroups take more), published
+        // SW_GRING - 1 generations ahead.  Once every data wave that has a
+        // wave-tile in generation t has posted its counts, one atomic reserves
+        // the output ranges of the whole generation.
+        u32 *gctr = &st->gen;
+        auto publish = [&](u32 t, u32 g) {
+            if (lane == 0) {
+                sh.gnum[t % SW_GRING] = g;
+                lds_release(&sh.gseq[t % SW_GRING], t + 1u);
+            }
+        };
+        if (lane < SW_GRING) sh.gseq[lane] = 0u;     // LDS keeps an earlier kernel's values
+        publish(0u, blockIdx.x);
         __syncthreads();
+        auto fetch = [&]() -> u32 {
+            u32 g = 0;
+            if (lane == 0) g = atomicAdd(gctr, 1u) + gridDim.x;
+            return __builtin_amdgcn_readfirstlane(__shfl(g, 0, WAVE));
+        };
+        for (u32 t = 1; t < SW_GRING - 1; ++t) publish(t, fetch());
         u64 *resv = &st->resv;
         for (u32 t = 0;; ++t) {
-            const u64 t0 = ((u64)t * gridDim.x + blockIdx.x) * (u64)SW_DW;
-            if (t0 >= nwt) break;
+            const u32 gt = __builtin_amdgcn_readfirstlane(sh.gnum[t % SW_GRING]);
+            const u64 t0 = (u64)gt * (u64)SW_DW;
+            if (t0 >= nwt) break;       // numbers only grow: nothing after it either
+            publish(t + SW_GRING - 1, fetch());
             const u32 expected = (u64)nwt - t0 < (u64)SW_DW ? (u32)((u64)nwt - t0) : (u32)SW_DW;
             const bool mine = lane < expected;
-            WSlot *S = &sh.slot[mine ? lane : 0u][t & 1u];
+            WSlot *S = &sh.slot[mine ? lane : 0u][t % SW_SLOTS];
             while (ballot(mine && lds_acquire(&S->state) != 1u)) __builtin_amdgcn_s_sleep(1);
             const u32 c = mine ? S->cnt : 0u;
             const u32 ca = c & 0xFFFFu, cb = c >> 16;
@@ -897,11 +924,16 @@ __device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const P
 
     // ---------------- data waves ----------------
     const u32 dw = w - 1;
-    if (lane == 0) {
-        sh.slot[dw][0].state = 0u;
-        sh.slot[dw][1].state = 0u;
-    }
+    if (lane == 0)
+        for (int i = 0; i < SW_SLOTS; ++i) sh.slot[dw][i].state = 0u;
     __syncthreads();
+    // wave-tile of this data wave in the workgroup's generation t (or nwt)
+    auto tile_of = [&](u32 t) -> u32 {
+        u32 *q = &sh.gseq[t % SW_GRING];
+        while (lds_acquire(q) != t + 1u) __builtin_amdgcn_s_sleep(1);
+        const u64 wt = (u64)__builtin_amdgcn_readfirstlane(sh.gnum[t % SW_GRING]) * SW_DW + dw;
+        return wt < (u64)nwt ? (u32)wt : nwt;
+    };
     const u64 cursor = st->cursor;
     const u64 hs_T = st->hs_T;
     const u32 di = (src == 1) ? 1u : 0u;
@@ -1047,19 +1079,25 @@ __device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const P
             auto abit = [&](int j) -> bool { return ((((j < 32) ? A0 : A1) >> (31 - (j & 31))) & 1u) != 0; };
             if (!wkeys) {
                 // positions only (band input: still in registers)
-                static_for<COLS>([&](auto jc) {
-                    constexpr int j = decltype(jc)::value;
-                    const bool ia = abit(j);
-                    const u64 ma = ballot(ia);
-                    if (ma) {
-                        if (ia) {
-                            const u32 q = mbcnt_add(ma, ra);
-                            if (fits || abase + q < a.k)
-                                oi[q] = KIND == 2 ? ix[j] : (u32)wb + (u32)(j * WAVE) + ln;
+                auto put = [&](auto clip_tag) {
+                    constexpr bool CLIP = decltype(clip_tag)::value;
+                    const u32 lim = CLIP ? (u32)(a.k - abase) : 0u;   // abase < k when clipping
+                    static_for<COLS>([&](auto jc) {
+                        constexpr int j = decltype(jc)::value;
+                        const bool ia = abit(j);
+                        const u64 ma = ballot(ia);
+                        if (ma) {
+                            if (ia) {
+                                const u32 q = mbcnt_add(ma, ra);
+                                if (!CLIP || q < lim)
+                                    oi[q] = KIND == 2 ? ix[j] : (u32)wb + (u32)(j * WAVE) + ln;
+                            }
+                            ra += (u32)__popcll(ma);
                         }
-                        ra += (u32)__popcll(ma);
-                    }
-                });
+                    });
+                };
+                if (fits) put(std::false_type());
+                else if (abase < a.k) put(std::true_type());
             } else {
                 // keys are read again: per group of columns all loads first,
                 // then one wait
@@ -1135,32 +1173,40 @@ __device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const P
         if (lane == 0) lds_release(&P.state, 0u);
     };
 
-    u32 cur = blockIdx.x * (u32)SW_DW + dw;
+    u32 cur = tile_of(0u);
     if (cur < nwt) issue(cur);
-    u32 pa0 = 0, pa1 = 0, prev = 0;
-    bool have_prev = false;
+    // key input: pass 2 of the wave-tile of iteration i runs in iteration
+    // i + 2 (q1 = iteration - 2, q0 = iteration - 1)
+    u32 q0t = 0, q0a0 = 0, q0a1 = 0, q1t = 0, q1a0 = 0, q1a1 = 0, npend = 0;
     for (u32 it = 0;; ++it) {
+        const u32 sl = it % SW_SLOTS;
         u32 ca0 = 0, ca1 = 0;
         if (KIND == 2) {
             // band input: the reservation wait is exposed, band positions need no reload
             if (cur >= nwt) break;
-            count_tile(cur, sh.slot[dw][it & 1u], ca0, ca1);
-            write_tile(cur, sh.slot[dw][it & 1u], ca0, ca1);
-            cur += stride;
+            count_tile(cur, sh.slot[dw][sl], ca0, ca1);
+            write_tile(cur, sh.slot[dw][sl], ca0, ca1);
+            cur = tile_of(it + 1u);
             asm volatile("" ::: "memory");
             if (cur < nwt) issue(cur);
             continue;
         }
-        if (cur < nwt) count_tile(cur, sh.slot[dw][it & 1u], ca0, ca1);
-        if (have_prev) write_tile(prev, sh.slot[dw][(it - 1) & 1u], pa0, pa1);
-        if (cur >= nwt) break;
-        const u32 nxt = cur + stride;
+        const bool have = cur < nwt;
+        if (have) count_tile(cur, sh.slot[dw][sl], ca0, ca1);
+        if (npend == 2) {
+            write_tile(q1t, sh.slot[dw][(it + 1) % SW_SLOTS], q1a0, q1a1);
+            npend = 1;
+        }
+        if (!have) {
+            if (npend == 1) write_tile(q0t, sh.slot[dw][(it + 2) % SW_SLOTS], q0a0, q0a1);
+            break;
+        }
+        const u32 nxt = tile_of(it + 1u);
         asm volatile("" ::: "memory");   // the next loads stay after pass 2 (register budget)
         if (nxt < nwt) issue(nxt);
-        have_prev = true;
-        prev = cur;
-        pa0 = ca0;
-        pa1 = ca1;
+        q1t = q0t; q1a0 = q0a0; q1a1 = q0a1;
+        q0t = cur; q0a0 = ca0; q0a1 = ca1;
+        ++npend;
         cur = nxt;
     }
 }

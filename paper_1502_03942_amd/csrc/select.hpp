@@ -16,7 +16,8 @@ constexpr int SW_COLS_IN = 64;                 // input keys per data-wave lane 
 constexpr int SW_COLS_BAND = 32;               // band pairs per data-wave lane per tile
 constexpr int SW_TILE_IN = SW_DW * 64 * SW_COLS_IN;     // 61440 keys
 constexpr int SW_TILE_BAND = SW_DW * 64 * SW_COLS_BAND; // 30720 pairs
-constexpr int SW_STASH = 384;                  // b pairs kept in LDS per wave-tile
+constexpr int SW_STASH = 320;                  // b pairs kept in LDS per wave-tile
+constexpr int SW_SLOTS = 3;                    // wave-tile slots per data wave (pass 2 trails by 2)
 constexpr int S_MAX = PV_THREADS * SEG_CAP;    // largest usable sample (16384)
 constexpr int R_TRACE = 32;                    // attempt records kept
 constexpr int TRACE_STRIDE = NSEG * SEG_CAP;   // sample positions per record
@@ -36,10 +37,12 @@ struct State {
     uint32_t na, nb, nrec, pad0;
     uint32_t l_ord, l_idx, r_ord, r_idx;
     uint32_t has_l, has_r, pad1, pad2;
-    uint64_t resv;              // sweep output reservations: |a| << 32 | |b|
     uint64_t hs_T;              // rate of the sample drawn from b (T = rho 2^32)
     uint32_t hs_count, pad4, pad5, pad6;   // elements taken into that sample
-    RoundRec rec[R_TRACE];
+    // counters hit by every sweep workgroup, each on a cache line of its own
+    alignas(128) uint64_t resv; // sweep output reservations: |a| << 32 | |b|
+    alignas(128) uint32_t gen;  // sweep generations handed out beyond the first
+    alignas(128) RoundRec rec[R_TRACE];
 };
 
 struct SelArgs {
