@@ -90,8 +90,7 @@ __device__ __forceinline__ void radix_select(const u64 (&v)[M], int cnt, const u
             u64 mn = ~0ull, mx = 0ull;
 #pragma unroll
             for (int j = 0; j < M; ++j) {
-                if (j >= cw) break;
-                if (j < cnt && rs_match(v[j], pref[t], lowb[t])) {
+                if (j < cw && j < cnt && rs_match(v[j], pref[t], lowb[t])) {
                     mn = v[j] < mn ? v[j] : mn;
                     mx = v[j] > mx ? v[j] : mx;
                 }
@@ -119,8 +118,7 @@ __device__ __forceinline__ void radix_select(const u64 (&v)[M], int cnt, const u
             sh[t] = hb >= RS_BITS - 1 ? hb - (RS_BITS - 1) : 0;
 #pragma unroll
             for (int j = 0; j < M; ++j) {
-                if (j >= cw) break;
-                if (j < cnt && rs_match(v[j], pref[t], lowb[t]))
+                if (j < cw && j < cnt && rs_match(v[j], pref[t], lowb[t]))
                     atomicAdd(&sm.rhist[t][(u32)(v[j] >> sh[t]) & (RS_BINS - 1)], 1u);
             }
         }
@@ -179,8 +177,7 @@ __device__ __forceinline__ void radix_select(const u64 (&v)[M], int cnt, const u
                 if (!gather[t]) continue;
 #pragma unroll
                 for (int j = 0; j < M; ++j) {
-                    if (j >= cw) break;
-                    if (j < cnt && rs_match(v[j], pref[t], lowb[t]))
+                    if (j < cw && j < cnt && rs_match(v[j], pref[t], lowb[t]))
                         sm.cand[t][atomicAdd(&sm.ccount[t], 1u)] = v[j];
                 }
             }
