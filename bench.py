@@ -160,7 +160,7 @@ def bench_select(args):
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        m = 1 << 23
+        m = 1 << 24
         sample = keys_np[:m]
         ks_s = [max(1, k * m // n) for k in ks]
         log("cpu baseline: oracle on %d keys" % m)
@@ -171,7 +171,7 @@ def bench_select(args):
         model, ncpu = cpu_info()
         cpu = {"value": round(len(ks_s) * m / dt / 1e9, 5), "unit": "Gkeys/s", "cores": 1,
                "kind": "oracle",
-               "sample": "first 2^23 keys of the same array, k scaled by 2^-5 to %s; full sort "
+               "sample": "first 2^24 keys of the same array, k scaled by 2^-4 to %s; full sort "
                          "by (value, position) per k, one thread; %.1f s; host %s (%d logical CPUs)"
                          % (ks_s, dt, model, ncpu)}
 
@@ -195,11 +195,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device copy (the reference kernel "
+                         "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the selection runs on a single device "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 2^30 bytes read, 2^30 bytes written")
+        del src, dst
     out = bench_select(args)
     print(json.dumps(out), flush=True)
 
