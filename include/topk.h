@@ -157,6 +157,37 @@ int topk_trace_sample(const topk_ctx *ctx, const void *workspace, uint64_t n,
  * *count = kernels recorded (only min(count, max) are written). */
 int topk_kernel_times(topk_ctx *ctx, float *ms, int32_t *kind, uint32_t max, uint32_t *count);
 
+/* ---- Row-wise top-k (a differentiable layer's forward and backward) ----
+ *
+ * topk_rows_fwd_f32: for every row b of scores[B][N] (row-major, f32), the k
+ * first elements of the row in selection order (the unique order by
+ * (key, position) of Section 2, as for topk_select_f32; with TOPK_LARGEST
+ * the largest keys first, NaN before everything), written in that order:
+ *   values  [B][k]  key bits copied from scores (-0.0 and NaN payloads kept)
+ *   indices [B][k]  column of each value (int64, the dtype torch.topk uses)
+ * so values are descending with ties by ascending column (TOPK_LARGEST), or
+ * ascending with ties by ascending column.  One workgroup per row: the
+ * candidates at or before the k-th of the threads' local minima are ranked
+ * exactly (see rows.hip); no workspace.  All pointers are device pointers;
+ * the call is asynchronous on `stream`; ctx may be NULL.  Limits: 1 <= k <=
+ * min(N, 1024), N <= 32768 (else TOPK_E_UNSUPPORTED).  flags: 0 or
+ * TOPK_LARGEST.  Returns TOPK_OK, TOPK_E_INVALID (null or misaligned pointer,
+ * B, N or k out of range, unknown flag), TOPK_E_UNSUPPORTED or TOPK_E_HIP. */
+int topk_rows_fwd_f32(topk_ctx *ctx, const float *scores, uint32_t B, uint32_t N,
+                      uint32_t k, uint32_t flags, float *values, int64_t *indices,
+                      hipStream_t stream);
+
+/* topk_scatter_bwd_f32: gradient of the row-wise top-k values with respect
+ * to the scores: grad_in[b][j] = grad_out[b][m] where indices[b][m] = j, and
+ * 0 elsewhere.  Every element of grad_in[B][N] is written exactly once (no
+ * separate clearing).  indices as returned by topk_rows_fwd_f32 (distinct
+ * within a row); entries outside [0, N) are ignored.  Device pointers,
+ * asynchronous on `stream`.  Returns TOPK_OK, TOPK_E_INVALID (null or
+ * misaligned pointer, B, N or k out of range), TOPK_E_UNSUPPORTED (more than
+ * 2^31 - 1 workgroups) or TOPK_E_HIP. */
+int topk_scatter_bwd_f32(const float *grad_out, const int64_t *indices, uint32_t B,
+                         uint32_t N, uint32_t k, float *grad_in, hipStream_t stream);
+
 const char *topk_strerror(int code);
 
 #ifdef __cplusplus

@@ -68,6 +68,8 @@ def lib():
                                     ctypes.POINTER(u32), vp]
     L.topk_trace_sample.argtypes = [vp, vp, u64, u32, vp, u32, ctypes.POINTER(u32), vp]
     L.topk_kernel_times.argtypes = [vp, vp, vp, u32, ctypes.POINTER(u32)]
+    L.topk_rows_fwd_f32.argtypes = [vp, vp, u32, u32, u32, u32, vp, vp, vp]
+    L.topk_scatter_bwd_f32.argtypes = [vp, vp, u32, u32, u32, vp, vp]
     L.topk_strerror.argtypes = [i32]
     L.topk_strerror.restype = ctypes.c_char_p
     _lib = L
@@ -196,3 +198,59 @@ def default_context(device=None):
 def select(keys, k, largest=False, write_keys=False):
     """Top-k selection of a 1-D CUDA tensor with the device's default context."""
     return default_context(keys.device).select(keys, k, largest=largest, write_keys=write_keys)
+
+
+# ---------------------------------------------------------------------------
+# Row-wise top-k and its gradient (a differentiable layer).
+# ---------------------------------------------------------------------------
+def rows_fwd(scores, k, largest=True):
+    """Row-wise top-k of a 2-D f32 CUDA tensor (topk_rows_fwd_f32).
+
+    Returns (values f32 [B, k], indices int64 [B, k]) in selection order:
+    values descending with ties by ascending column when ``largest``.
+    """
+    if scores.dim() != 2 or not scores.is_cuda or scores.dtype != torch.float32:
+        raise TopkError("rows_fwd: scores must be a 2-D float32 CUDA tensor")
+    scores = scores.contiguous()
+    B, N = scores.shape
+    values = torch.empty((B, k), dtype=torch.float32, device=scores.device)
+    indices = torch.empty((B, k), dtype=torch.int64, device=scores.device)
+    _check(lib().topk_rows_fwd_f32(None, _ptr(scores), B, N, k, TOPK_LARGEST if largest else 0,
+                                   _ptr(values), _ptr(indices), _stream(scores.device)))
+    return values, indices
+
+
+def scatter_bwd(grad_out, indices, n_cols):
+    """Dense gradient of row-wise top-k values (topk_scatter_bwd_f32)."""
+    if grad_out.dim() != 2 or grad_out.dtype != torch.float32 or indices.dtype != torch.int64:
+        raise TopkError("scatter_bwd: grad_out f32 [B, k] and indices int64 [B, k] expected")
+    grad_out = grad_out.contiguous()
+    indices = indices.contiguous()
+    B, k = grad_out.shape
+    grad_in = torch.empty((B, n_cols), dtype=torch.float32, device=grad_out.device)
+    _check(lib().topk_scatter_bwd_f32(_ptr(grad_out), _ptr(indices), B, n_cols, k,
+                                      _ptr(grad_in), _stream(grad_out.device)))
+    return grad_in
+
+
+class TopK(torch.autograd.Function):
+    """values, indices = TopK.apply(scores, k, largest): row-wise top-k whose
+    backward scatters the values' gradient back to the selected columns."""
+
+    @staticmethod
+    def forward(ctx, scores, k, largest=True):
+        values, indices = rows_fwd(scores, k, largest)
+        ctx.save_for_backward(indices)
+        ctx.n_cols = scores.shape[1]
+        ctx.mark_non_differentiable(indices)
+        return values, indices
+
+    @staticmethod
+    def backward(ctx, grad_values, grad_indices):
+        (indices,) = ctx.saved_tensors
+        return scatter_bwd(grad_values, indices, ctx.n_cols), None, None
+
+
+def topk(scores, k, largest=True):
+    """Differentiable row-wise top-k: (values, indices), like torch.topk(scores, k, dim=1)."""
+    return TopK.apply(scores, k, largest)
