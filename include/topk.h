@@ -55,6 +55,7 @@ extern "C" {
 #define TOPK_LARGEST 1u          /* select the k largest instead of the k smallest  */
 #define TOPK_WRITE_KEYS 4u       /* also write the selected keys (original bits)   */
 #define TOPK_TRACE 8u            /* record every round's sample in the workspace   */
+#define TOPK_GRAPH 16u           /* batched: launch through a cached hipGraph      */
 
 /* Device status word bits (written by every select call when status != NULL). */
 #define TOPK_STATUS_OK 0u
@@ -156,6 +157,40 @@ int topk_trace_sample(const topk_ctx *ctx, const void *workspace, uint64_t n,
  * 3 later sweep, 4 tail kernel).  Waits for the events; clears the record.
  * *count = kernels recorded (only min(count, max) are written). */
 int topk_kernel_times(topk_ctx *ctx, float *ms, int32_t *kind, uint32_t max, uint32_t *count);
+
+/* ---- Batched selection: many rows of uneven length, each with its own k ----
+ *
+ * topk_select_batched_f32: for every row r of a CSR batch, the k[r] smallest
+ * (largest with TOPK_LARGEST) keys of keys[row_off[r] .. row_off[r+1]) under
+ * the unique order by (key, column) of Section 2 (the same rule as
+ * topk_select_f32, with column = position inside the row).
+ *   keys     [row_off[rows]]  f32 keys of all rows, row after row
+ *   row_off  [rows + 1]       u64 row boundaries (non-decreasing)
+ *   k        [rows]           u32, 1 <= k[r] <= row length
+ *   out_off  [rows + 1]       u64 exclusive prefix sums of k (caller-computed)
+ *   out_idx  [out_off[rows]]  row r's selected columns at out_off[r] .. + k[r]:
+ *                             the columns below the row's lower pivot in
+ *                             column order, then the rest in column order
+ *   kth_key  [rows]           key of rank k[r] (bits as stored)
+ *   kth_idx  [rows]           its column
+ *   status   [1]              0, or TOPK_STATUS_BAD_ROW if some row had
+ *                             k = 0, k > length or length >= 2^32 (skipped)
+ *   workspace >= topk_batched_workspace_bytes(ctx, rows, flags), 256-aligned
+ * One persistent launch of 256-thread workgroups over the rows, longest rows
+ * first; each row by the sampling method with the workgroup as the machine
+ * (batched.hip).  Context parameters "bt_s_target", "bt_c_num",
+ * "bt_wg_per_cu", "bt_attempts" tune it.  flags: TOPK_LARGEST, TOPK_GRAPH
+ * (capture the four launches into a hipGraph on first use for this exact
+ * argument set and replay it afterwards; the ctx keeps the graph).  All
+ * pointers are device pointers; asynchronous on `stream`.  Returns TOPK_OK,
+ * TOPK_E_INVALID (null or misaligned pointer, rows = 0, unknown flag),
+ * TOPK_E_WORKSPACE or TOPK_E_HIP. */
+size_t topk_batched_workspace_bytes(const topk_ctx *ctx, uint32_t rows, uint32_t flags);
+int topk_select_batched_f32(topk_ctx *ctx, const float *keys, const uint64_t *row_off,
+                            uint32_t rows, const uint32_t *k, const uint64_t *out_off,
+                            uint32_t flags, uint32_t *out_idx, float *kth_key,
+                            uint32_t *kth_idx, uint32_t *status, void *workspace,
+                            size_t ws_bytes, hipStream_t stream);
 
 /* ---- Row-wise top-k (a differentiable layer's forward and backward) ----
  *

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libtopk.so")
 TOPK_LARGEST = 1
 TOPK_WRITE_KEYS = 4
 TOPK_TRACE = 8
+TOPK_GRAPH = 16
 STATUS_OK = 0
 STATUS_NO_CONVERGENCE = 1
 STATUS_BAD_ROW = 2
@@ -68,6 +69,9 @@ def lib():
                                     ctypes.POINTER(u32), vp]
     L.topk_trace_sample.argtypes = [vp, vp, u64, u32, vp, u32, ctypes.POINTER(u32), vp]
     L.topk_kernel_times.argtypes = [vp, vp, vp, u32, ctypes.POINTER(u32)]
+    L.topk_batched_workspace_bytes.argtypes = [vp, u32, u32]
+    L.topk_batched_workspace_bytes.restype = sz
+    L.topk_select_batched_f32.argtypes = [vp, vp, vp, u32, vp, vp, u32, vp, vp, vp, vp, vp, sz, vp]
     L.topk_rows_fwd_f32.argtypes = [vp, vp, u32, u32, u32, u32, vp, vp, vp]
     L.topk_scatter_bwd_f32.argtypes = [vp, vp, u32, u32, u32, vp, vp]
     L.topk_strerror.argtypes = [i32]
@@ -158,6 +162,47 @@ class Context:
         return res
 
     KERNEL_KINDS = ("pivot_first", "pivot", "sweep_first", "sweep", "tail")
+
+    def batched_workspace(self, rows, flags=0):
+        nb = int(lib().topk_batched_workspace_bytes(self._h, rows, flags))
+        return torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device)
+
+    def select_batched(self, keys, row_off, k, out_off=None, largest=False, graph=False,
+                       workspace=None, out=None):
+        """Per-row top-k of a CSR batch (topk_select_batched_f32).
+
+        keys f32 [sum len], row_off int64 [R+1], k int32 [R] (all CUDA); out_off
+        int64 [R+1] (exclusive prefix of k) is computed on the device if None.
+        Returns a dict: ``idx`` (int32 holding u32 columns, length sum k),
+        ``kth_key`` f32 [R], ``kth_idx`` (int32 holding u32) [R], ``status``,
+        ``out_off``.  ``out`` (a dict from an earlier call with the same shapes)
+        reuses its buffers, which keeps a captured graph valid.
+        """
+        R = row_off.numel() - 1
+        if keys.dtype != torch.float32 or keys.dim() != 1 or not keys.is_cuda:
+            raise TopkError("select_batched: keys must be a 1-D float32 CUDA tensor")
+        if row_off.dtype not in (torch.int64, torch.uint64) or k.dtype not in (torch.int32, torch.uint32):
+            raise TopkError("select_batched: row_off int64 [R+1] and k int32 [R] expected")
+        if out is None:
+            if out_off is None:
+                out_off = torch.zeros(R + 1, dtype=torch.int64, device=keys.device)
+                out_off[1:] = torch.cumsum(k.to(torch.int64), 0)
+            total = int(out_off[-1].item())
+            out = {"idx": torch.empty(max(total, 1), dtype=torch.int32, device=keys.device),
+                   "kth_key": torch.empty(R, dtype=torch.float32, device=keys.device),
+                   "kth_idx": torch.empty(R, dtype=torch.int32, device=keys.device),
+                   "status": torch.zeros(1, dtype=torch.int32, device=keys.device),
+                   "out_off": out_off}
+        ws = workspace if workspace is not None else out.get("workspace")
+        if ws is None:
+            ws = self.batched_workspace(R)
+        out["workspace"] = ws
+        flags = (TOPK_LARGEST if largest else 0) | (TOPK_GRAPH if graph else 0)
+        _check(lib().topk_select_batched_f32(
+            self._h, _ptr(keys), _ptr(row_off), R, _ptr(k), _ptr(out["out_off"]), flags,
+            _ptr(out["idx"]), _ptr(out["kth_key"]), _ptr(out["kth_idx"]), _ptr(out["status"]),
+            _ptr(ws), ws.numel(), _stream(keys.device)))
+        return out
 
     def kernel_times(self, max_records=1 << 16):
         """Durations (ms) of the kernels recorded with param "timing" > 0 since

@@ -1,0 +1,515 @@
+// Batched selection: many rows of uneven length, each with its own k, in one
+// persistent launch (§1: many similar selections solved together).
+//
+// Rows are ordered longest first (a counting sort by floor(log2 len)) and
+// taken round-robin by a persistent grid of 256-thread workgroups, so no row
+// needs an atomic.  One workgroup solves a row by the sampling method of §2
+// with the workgroup as the machine:
+//   - a row of at most BT_CAP keys is the base case: its (ord, column) pairs go
+//     to LDS and the pair of rank k is found exactly;
+//   - a longer row draws a Bernoulli sample of about bt_s_target keys
+//     (geometric skips, one segment per thread), takes the pivots at sample
+//     ranks k s / len -/+ Delta, and sweeps the row once: the part below the
+//     lower pivot goes straight to the output (in column order), the band
+//     between the pivots to LDS.  If the band brackets rank k and fits, the
+//     band is finished like a short row.  Otherwise the round is repeated with
+//     a new sample (spread doubled after a miss, halved after an overflow) and
+//     after bt_attempts rounds an exact radix select over the row finishes it.
+// Every decision compares the composite key (ord, column), the unique order
+// of §2, so the selected set is exactly the oracle's.
+//
+// Output per row: out_idx[out_off[r] .. + k) holds the selected columns: those
+// below the lower pivot in column order, then the rest in column order (a row
+// finished directly or by the exact fallback: all in column order);
+// kth_key[r] / kth_idx[r] the pair of rank k (key bits as stored).
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <vector>
+
+#include "common.hpp"
+#include "ctx.hpp"
+#include "../../include/topk.h"
+
+namespace topk {
+
+constexpr int BT_THREADS = 256;                 // 4 waves
+constexpr int BT_WAVES = BT_THREADS / WAVE;
+constexpr u32 BT_CAP = 4096;                    // pairs in LDS: a short row or a band
+constexpr int BT_BITS = 11;                     // radix digit
+constexpr u32 BT_BINS = 1u << BT_BITS;
+constexpr int BT_SEG = 8;                       // sample slots per thread
+constexpr int BT_IPT = 16;                      // keys per thread per sweep step
+constexpr u32 BT_STEP = BT_THREADS * BT_IPT;
+constexpr int BT_NCLS = 34;                     // length classes 0 (empty) .. 33
+constexpr int BT_HIST_THREADS = 1024;
+
+struct BtShared {
+    u64 buf[BT_CAP];
+    u32 hist[BT_BINS];
+    u64 cand[WAVE];
+    u64 rmin, rmax, found;
+    u32 ccount, sel_bin, sel_before, sel_count;
+    u32 scan[BT_WAVES];
+};
+
+struct BtArgs {
+    const u32 *keys;
+    const u64 *row_off;
+    const u32 *k;
+    const u64 *out_off;
+    u32 rows, flags;
+    u32 *out_idx, *kth_key, *kth_idx, *status;
+    u32 *cls_cnt, *cls_fill, *order;
+    u64 seed;
+    u32 s_target, c_num, attempts;
+};
+
+__device__ __forceinline__ u32 len_class(u64 len)
+{
+    const u32 c = len == 0 ? 0u : 64u - (u32)__clzll((long long)len);
+    return c < (u32)BT_NCLS ? c : (u32)BT_NCLS - 1;
+}
+
+__device__ __forceinline__ bool bt_match(u64 x, u64 pref, int lowb)
+{
+    return lowb >= 64 || (x >> lowb) == (pref >> lowb);
+}
+
+// Pair of 0-based rank `rank` among src(0 .. n-1) (distinct pairs): radix
+// select over the RS-style adaptive window below the common prefix of the
+// candidates' minimum and maximum; a bucket of at most 64 is ranked by one
+// wave.  All threads call it and get the result.
+template <class SRC>
+__device__ u64 bt_select(SRC src, u32 n, u64 rank, BtShared &sh)
+{
+    const u32 tid = threadIdx.x, lane = lane_id();
+    const u32 w = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    u64 pref = 0;
+    int lowb = 64;
+    for (u32 i = tid; i < BT_BINS; i += BT_THREADS) sh.hist[i] = 0u;
+    for (int pass = 0; pass < 16; ++pass) {
+        if (tid == 0) {
+            sh.rmin = ~0ull;
+            sh.rmax = 0ull;
+            sh.ccount = 0u;
+        }
+        __syncthreads();
+        u64 mn = ~0ull, mx = 0ull;
+        for (u32 i = tid; i < n; i += BT_THREADS) {
+            const u64 x = src(i);
+            if (bt_match(x, pref, lowb)) {
+                mn = x < mn ? x : mn;
+                mx = x > mx ? x : mx;
+            }
+        }
+        mn = wave_min_u64(mn);
+        mx = wave_max_u64(mx);
+        if (lane == 0 && mn <= mx) {
+            atomicMin((unsigned long long *)&sh.rmin, (unsigned long long)mn);
+            atomicMax((unsigned long long *)&sh.rmax, (unsigned long long)mx);
+        }
+        __syncthreads();
+        const u64 gmn = sh.rmin, gmx = sh.rmax;
+        if (gmn == gmx) {
+            __syncthreads();            // everyone has read them before the next use
+            return gmn;
+        }
+        const int hb = 63 - __clzll((long long)(gmn ^ gmx));
+        const int sh_ = hb >= BT_BITS - 1 ? hb - (BT_BITS - 1) : 0;
+        for (u32 i = tid; i < n; i += BT_THREADS) {
+            const u64 x = src(i);
+            if (bt_match(x, pref, lowb)) atomicAdd(&sh.hist[(u32)(x >> sh_) & (BT_BINS - 1)], 1u);
+        }
+        __syncthreads();
+        // thread t covers bins [8t, 8t + 8)
+        u32 c[8], csum = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            c[q] = sh.hist[tid * 8 + q];
+            sh.hist[tid * 8 + q] = 0u;       // clean for the next pass
+            csum += c[q];
+        }
+        u32 tot;
+        u32 before = block_excl_scan<BT_THREADS>(csum, sh.scan, &tot);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if ((u64)before <= rank && rank < (u64)before + c[q]) {
+                sh.sel_bin = tid * 8 + q;
+                sh.sel_before = before;
+                sh.sel_count = c[q];
+            }
+            before += c[q];
+        }
+        __syncthreads();
+        const int top = sh_ + BT_BITS;
+        pref = (top >= 64 ? 0ull : (gmn >> top) << top) | ((u64)sh.sel_bin << sh_);
+        lowb = sh_;
+        rank -= sh.sel_before;
+        if (sh.sel_count <= (u32)WAVE) {
+            for (u32 i = tid; i < n; i += BT_THREADS) {
+                const u64 x = src(i);
+                if (bt_match(x, pref, lowb)) sh.cand[atomicAdd(&sh.ccount, 1u)] = x;
+            }
+            __syncthreads();
+            if (w == 0) {
+                const u32 m = sh.ccount;
+                const u64 mine = lane < m ? sh.cand[lane] : ~0ull;
+                const u32 mlo = (u32)mine, mhi = (u32)(mine >> 32);
+                u32 below = 0;
+                for (u32 i = 0; i < m; ++i) {
+                    const u64 o = ((u64)(u32)__builtin_amdgcn_readlane((int)mhi, (int)i) << 32) |
+                                  (u32)__builtin_amdgcn_readlane((int)mlo, (int)i);
+                    below += o < mine ? 1u : 0u;
+                }
+                if (lane < m && (u64)below == rank) sh.found = mine;
+            }
+            __syncthreads();
+            const u64 f = sh.found;
+            __syncthreads();
+            return f;
+        }
+    }
+    return sh.found;
+}
+
+// Write the columns of the pairs <= tau among src(0 .. n-1), in source order,
+// to out[0 ..) (at most `limit`).  Thread t takes runs of BT_IPT consecutive
+// pairs of each step, so source order is thread order within a step.
+template <class SRC>
+__device__ void bt_emit(SRC src, u32 n, u64 tau, u32 *out, u32 limit, BtShared &sh)
+{
+    const u32 tid = threadIdx.x;
+    u32 cur = 0;
+    for (u32 s0 = 0; s0 < n; s0 += BT_STEP) {
+        u64 v[BT_IPT];
+        u32 c = 0;
+#pragma unroll
+        for (int j = 0; j < BT_IPT; ++j) {
+            const u32 i = s0 + tid * BT_IPT + (u32)j;
+            v[j] = i < n ? src(i) : ~0ull;
+            c += (i < n && v[j] <= tau) ? 1u : 0u;
+        }
+        u32 tot;
+        u32 pos = cur + block_excl_scan<BT_THREADS>(c, sh.scan, &tot);
+#pragma unroll
+        for (int j = 0; j < BT_IPT; ++j) {
+            const u32 i = s0 + tid * BT_IPT + (u32)j;
+            if (i < n && v[j] <= tau) {
+                if (pos < limit) out[pos] = (u32)v[j];
+                ++pos;
+            }
+        }
+        cur += tot;
+    }
+}
+
+// Geometric-skip Bernoulli sample of a row (rate s_target / len): thread t
+// samples its segment [t L, min(t L + L, len)), L = ceil(len / 256), with
+// skips 1 + floor(ln U / ln(1 - rho)), U from Philox4x32-10 at counter
+// (j / 4, t, tag, row), key = seed; at most BT_SEG per segment.
+__device__ __forceinline__ int bt_sample(u32 t, u64 len, u32 s_target, u64 seed, u32 tag,
+                                         u32 row, u32 (&pos)[BT_SEG])
+{
+    const double rho = (double)s_target / (double)len;
+    const u64 L = (len + BT_THREADS - 1) / BT_THREADS;
+    const u64 s0 = (u64)t * L;
+    const u64 e0 = s0 + L < len ? s0 + L : len;
+    if (s0 >= e0) return 0;
+    const double ln1mrho = log1p(-rho);
+    i64 p = (i64)s0 - 1;
+    int cnt = 0;
+    bool stop = false;
+    uint4 r4 = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int j = 0; j < BT_SEG; ++j) {
+        if (!stop) {
+            if ((j & 3) == 0)
+                r4 = philox4x32_10(make_uint4((u32)(j >> 2), t, tag, row), (u32)seed, (u32)(seed >> 32));
+            const u32 w = (j & 3) == 0 ? r4.x : (j & 3) == 1 ? r4.y : (j & 3) == 2 ? r4.z : r4.w;
+            const double u = ((double)w + 0.5) * (1.0 / 4294967296.0);
+            const double q = log(u) / ln1mrho;
+            if (q >= (double)((i64)e0 - 1 - p)) {
+                stop = true;
+            } else {
+                p = p + 1 + (i64)q;
+                pos[j] = (u32)p;
+                cnt = j + 1;
+            }
+        }
+    }
+    return cnt;
+}
+
+template <bool LARGEST>
+__device__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
+{
+    const u32 tid = threadIdx.x;
+    const u64 off = a.row_off[r];
+    const u64 len64 = a.row_off[r + 1] - off;
+    const u32 k = a.k[r];
+    if (k == 0 || (u64)k > len64 || len64 > 0xFFFFFFFFull) {
+        if (tid == 0) atomicOr(a.status, (u32)TOPK_STATUS_BAD_ROW);
+        return;
+    }
+    const u32 len = (u32)len64;
+    const u32 *__restrict__ row = a.keys + off;
+    u32 *__restrict__ out = a.out_idx + a.out_off[r];
+    auto gsrc = [&](u32 i) -> u64 { return pack(key_ord<true, LARGEST>(row[i]), i); };
+    auto lsrc = [&](u32 i) -> u64 { return sh.buf[i]; };
+
+    u32 na = 0, nb = len;
+    bool in_lds = false;
+    if (len <= BT_CAP) {
+        for (u32 i = tid; i < len; i += BT_THREADS) sh.buf[i] = gsrc(i);
+        __syncthreads();
+        in_lds = true;
+    } else {
+        u32 c_num = a.c_num;
+        for (u32 att = 0; att < a.attempts && !in_lds; ++att) {
+            // sample -> LDS, compacted
+            u32 pos[BT_SEG];
+            const int cnt = bt_sample(tid, len, a.s_target, a.seed, att, r, pos);
+            u32 s;
+            const u32 at = block_excl_scan<BT_THREADS>((u32)cnt, sh.scan, &s);
+#pragma unroll
+            for (int j = 0; j < BT_SEG; ++j)
+                if (j < cnt) sh.buf[at + (u32)j] = gsrc(pos[j]);
+            __syncthreads();
+            i64 lo, hi;
+            pivot_ranks(s, k, len, c_num, lo, hi);
+            const bool hl = lo >= 0, hr = hi < (i64)s;
+            const u64 L = hl ? bt_select(lsrc, s, (u64)lo, sh) : 0ull;
+            const u64 R = hr ? bt_select(lsrc, s, (u64)hi, sh) : ~0ull;
+            // one sweep: below L -> output, [L, R] -> LDS band
+            u32 ca = 0, cb = 0;
+            for (u32 s0 = 0; s0 < len; s0 += BT_STEP) {
+                u64 v[BT_IPT];
+                u32 ta = 0, tb = 0;
+#pragma unroll
+                for (int j = 0; j < BT_IPT; ++j) {
+                    const u32 i = s0 + tid * BT_IPT + (u32)j;
+                    v[j] = i < len ? gsrc(i) : ~0ull;
+                    const bool inb = i < len && !(hl && v[j] < L) && !(hr && v[j] > R);
+                    ta += (i < len && hl && v[j] < L) ? 1u : 0u;
+                    tb += inb ? 1u : 0u;
+                }
+                u32 tot;
+                const u32 ex = block_excl_scan<BT_THREADS>(ta | (tb << 16), sh.scan, &tot);
+                u32 pa = ca + (ex & 0xFFFFu), pb = cb + (ex >> 16);
+#pragma unroll
+                for (int j = 0; j < BT_IPT; ++j) {
+                    const u32 i = s0 + tid * BT_IPT + (u32)j;
+                    if (i < len) {
+                        if (hl && v[j] < L) {
+                            if (pa < k) out[pa] = i;
+                            ++pa;
+                        } else if (!(hr && v[j] > R)) {
+                            if (pb < BT_CAP) sh.buf[pb] = v[j];
+                            ++pb;
+                        }
+                    }
+                }
+                ca += tot & 0xFFFFu;
+                cb += tot >> 16;
+            }
+            __syncthreads();
+            if (ca >= k || ca + cb < k) {
+                c_num *= 2;                  // the pivots missed rank k: wider
+            } else if (cb > BT_CAP) {
+                c_num = c_num > 1 ? c_num / 2 : 1;   // band too wide for LDS: narrower
+            } else {
+                na = ca;
+                nb = cb;
+                in_lds = true;
+            }
+        }
+    }
+    u64 tau;
+    if (in_lds) {
+        tau = bt_select(lsrc, nb, (u64)(k - na - 1), sh);
+        bt_emit(lsrc, nb, tau, out + na, k - na, sh);
+    } else {
+        // exact fallback over the row
+        tau = bt_select(gsrc, len, (u64)(k - 1), sh);
+        bt_emit(gsrc, len, tau, out, k, sh);
+    }
+    if (tid == 0) {
+        a.kth_idx[r] = (u32)tau;
+        a.kth_key[r] = row[(u32)tau];
+    }
+    __syncthreads();
+}
+
+template <bool LARGEST>
+__global__ __launch_bounds__(BT_THREADS) void k_batched(BtArgs a)
+{
+    __shared__ BtShared sh;
+    for (u32 p = blockIdx.x; p < a.rows; p += gridDim.x) bt_row<LARGEST>(a, a.order[p], sh);
+}
+
+// Zero the class counters and the status word (a kernel, so the call can be
+// captured in a graph without memset nodes).
+__global__ void k_bt_init(BtArgs a)
+{
+    const u32 t = threadIdx.x;
+    if (t < BT_NCLS) {
+        a.cls_cnt[t] = 0u;
+        a.cls_fill[t] = 0u;
+    }
+    if (t == 0) *a.status = 0u;
+}
+
+// Rows per length class (workgroup histogram, one global add per class).
+__global__ __launch_bounds__(BT_HIST_THREADS) void k_bt_hist(BtArgs a)
+{
+    __shared__ u32 h[BT_NCLS];
+    const u32 t = threadIdx.x, r = blockIdx.x * BT_HIST_THREADS + t;
+    if (t < BT_NCLS) h[t] = 0u;
+    __syncthreads();
+    if (r < a.rows) atomicAdd(&h[len_class(a.row_off[r + 1] - a.row_off[r])], 1u);
+    __syncthreads();
+    if (t < BT_NCLS && h[t]) atomicAdd(&a.cls_cnt[t], h[t]);
+}
+
+// order[]: rows by decreasing length class (a counting sort; rows of one class
+// in no particular order).
+__global__ __launch_bounds__(BT_HIST_THREADS) void k_bt_order(BtArgs a)
+{
+    __shared__ u32 h[BT_NCLS], base[BT_NCLS];
+    const u32 t = threadIdx.x, r = blockIdx.x * BT_HIST_THREADS + t;
+    if (t < BT_NCLS) h[t] = 0u;
+    __syncthreads();
+    u32 cls = 0, local = 0;
+    if (r < a.rows) {
+        cls = len_class(a.row_off[r + 1] - a.row_off[r]);
+        local = atomicAdd(&h[cls], 1u);
+    }
+    __syncthreads();
+    if (t < BT_NCLS) {
+        // classes above t come first
+        u32 start = 0;
+        for (int c = BT_NCLS - 1; c > (int)t; --c) start += a.cls_cnt[c];
+        base[t] = h[t] ? start + atomicAdd(&a.cls_fill[t], h[t]) : 0u;
+    }
+    __syncthreads();
+    if (r < a.rows) a.order[base[cls] + local] = r;
+}
+
+}  // namespace topk
+
+using namespace topk;
+
+namespace {
+
+constexpr size_t BT_ALIGN = 256;
+inline size_t bt_align(size_t x) { return (x + BT_ALIGN - 1) / BT_ALIGN * BT_ALIGN; }
+
+struct BtLayout {
+    size_t cnt, fill, order, total;
+};
+
+BtLayout bt_layout(uint32_t rows)
+{
+    BtLayout L{};
+    size_t off = 0;
+    L.cnt = off;
+    off = bt_align(off + BT_NCLS * sizeof(uint32_t));
+    L.fill = off;
+    off = bt_align(off + BT_NCLS * sizeof(uint32_t));
+    L.order = off;
+    off = bt_align(off + (size_t)rows * sizeof(uint32_t));
+    L.total = off;
+    return L;
+}
+
+hipError_t bt_enqueue(const BtArgs &a, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bt_init, dim3(1), dim3(64), 0, s, a);
+    const u32 hb = (a.rows + BT_HIST_THREADS - 1) / BT_HIST_THREADS;
+    hipLaunchKernelGGL(k_bt_hist, dim3(hb), dim3(BT_HIST_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_bt_order, dim3(hb), dim3(BT_HIST_THREADS), 0, s, a);
+    if (a.flags & TOPK_LARGEST)
+        hipLaunchKernelGGL((k_batched<true>), dim3(grid), dim3(BT_THREADS), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_batched<false>), dim3(grid), dim3(BT_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" size_t topk_batched_workspace_bytes(const topk_ctx *ctx, uint32_t rows, uint32_t flags)
+{
+    (void)flags;
+    if (!ctx) return 0;
+    return bt_layout(rows).total;
+}
+
+extern "C" int topk_select_batched_f32(topk_ctx *c, const float *keys, const uint64_t *row_off,
+                                       uint32_t rows, const uint32_t *k, const uint64_t *out_off,
+                                       uint32_t flags, uint32_t *out_idx, float *kth_key,
+                                       uint32_t *kth_idx, uint32_t *status, void *workspace,
+                                       size_t ws_bytes, hipStream_t stream)
+{
+    if (!c || !keys || !row_off || !k || !out_off || !out_idx || !kth_key || !kth_idx ||
+        !status || !workspace)
+        return TOPK_E_INVALID;
+    if (rows == 0) return TOPK_E_INVALID;
+    if (flags & ~(uint32_t)(TOPK_LARGEST | TOPK_GRAPH)) return TOPK_E_INVALID;
+    if (((uintptr_t)keys & 3u) || ((uintptr_t)row_off & 7u) || ((uintptr_t)out_off & 7u) ||
+        ((uintptr_t)workspace & (BT_ALIGN - 1)))
+        return TOPK_E_INVALID;
+    const BtLayout L = bt_layout(rows);
+    if (ws_bytes < L.total) return TOPK_E_WORKSPACE;
+    char *w = (char *)workspace;
+    BtArgs a{};
+    a.keys = (const u32 *)keys;
+    a.row_off = (const u64 *)row_off;
+    a.k = k;
+    a.out_off = (const u64 *)out_off;
+    a.rows = rows;
+    a.flags = flags & TOPK_LARGEST;
+    a.out_idx = out_idx;
+    a.kth_key = (u32 *)kth_key;
+    a.kth_idx = kth_idx;
+    a.status = status;
+    a.cls_cnt = (u32 *)(w + L.cnt);
+    a.cls_fill = (u32 *)(w + L.fill);
+    a.order = (u32 *)(w + L.order);
+    a.seed = c->seed;
+    a.s_target = (u32)c->bt_s_target;
+    a.c_num = (u32)c->bt_c_num;
+    a.attempts = (u32)c->bt_attempts;
+    if (hipSetDevice(c->device) != hipSuccess) return TOPK_E_HIP;
+    const int grid = (int)(c->num_cu * c->bt_wg_per_cu);
+    if (!(flags & TOPK_GRAPH))
+        return bt_enqueue(a, grid, stream) == hipSuccess ? TOPK_OK : TOPK_E_HIP;
+
+    // one graph per distinct argument set: captured once, then replayed
+    std::vector<uint64_t> key = {
+        (uint64_t)(uintptr_t)keys, (uint64_t)(uintptr_t)row_off, rows, (uint64_t)(uintptr_t)k,
+        (uint64_t)(uintptr_t)out_off, a.flags, (uint64_t)(uintptr_t)out_idx,
+        (uint64_t)(uintptr_t)kth_key, (uint64_t)(uintptr_t)kth_idx, (uint64_t)(uintptr_t)status,
+        (uint64_t)(uintptr_t)workspace, a.seed, a.s_target, a.c_num, a.attempts, (uint64_t)grid};
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        if (!c->capture_stream &&
+            hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess)
+            return TOPK_E_HIP;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        if (hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return TOPK_E_HIP;
+        const hipError_t e1 = bt_enqueue(a, grid, c->capture_stream);
+        const hipError_t e2 = hipStreamEndCapture(c->capture_stream, &g);
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return TOPK_E_HIP;
+        }
+        const hipError_t e3 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e3 != hipSuccess) return TOPK_E_HIP;
+        it = c->graphs.emplace(key, ge).first;
+    }
+    return hipGraphLaunch(it->second, stream) == hipSuccess ? TOPK_OK : TOPK_E_HIP;
+}

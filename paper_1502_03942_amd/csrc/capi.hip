@@ -10,19 +10,9 @@
 
 #include "../../include/topk.h"
 #include "select.hpp"
+#include "ctx.hpp"
 
 using namespace topk;
-
-struct topk_ctx {
-    int device;
-    uint64_t seed;
-    int64_t s_target, c_num, t_fin, r_max, r_fast, band_div, tail_max, timing;
-    int num_cu;
-    // kernel timing: event pairs recorded by calls since the last read-out
-    std::vector<hipEvent_t> ev;
-    std::vector<int> ev_kind;
-    int ev_used = 0;
-};
 
 namespace {
 
@@ -200,6 +190,10 @@ int topk_create(topk_ctx **out, int hip_device, uint64_t seed)
     c->band_div = 4;
     c->tail_max = 65536;
     c->timing = 0;
+    c->bt_s_target = 1024;
+    c->bt_c_num = 24;
+    c->bt_wg_per_cu = 3;
+    c->bt_attempts = 4;
     c->num_cu = ncu;
     *out = c;
     return TOPK_OK;
@@ -209,6 +203,8 @@ void topk_destroy(topk_ctx *c)
 {
     if (!c) return;
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     delete c;
 }
 
@@ -224,6 +220,10 @@ int topk_set_param(topk_ctx *c, const char *name, int64_t v)
         {"band_div", &c->band_div, 1, 64},
         {"tail_max", &c->tail_max, 0, (int64_t)1 << 32},
         {"timing", &c->timing, 0, 2},
+        {"bt_s_target", &c->bt_s_target, 64, 2048},
+        {"bt_c_num", &c->bt_c_num, 4, 4096},
+        {"bt_wg_per_cu", &c->bt_wg_per_cu, 1, 8},
+        {"bt_attempts", &c->bt_attempts, 1, 16},
     };
     if (strcmp(name, "seed") == 0) { c->seed = (uint64_t)v; return TOPK_OK; }
     for (auto &e : tab) {
@@ -244,6 +244,8 @@ int topk_get_param(const topk_ctx *c, const char *name, int64_t *v)
         {"s_target", c->s_target}, {"c_num", c->c_num}, {"t_fin", c->t_fin},
         {"r_max", c->r_max}, {"r_fast", c->r_fast}, {"band_div", c->band_div},
         {"tail_max", c->tail_max}, {"timing", c->timing},
+        {"bt_s_target", c->bt_s_target}, {"bt_c_num", c->bt_c_num},
+        {"bt_wg_per_cu", c->bt_wg_per_cu}, {"bt_attempts", c->bt_attempts},
     };
     for (auto &e : tab) {
         if (strcmp(name, e.n) == 0) { *v = e.val; return TOPK_OK; }

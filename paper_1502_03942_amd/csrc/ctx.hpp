@@ -1,0 +1,25 @@
+// Host state behind the opaque topk_ctx of the C-ABI (not part of the API).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <tuple>
+#include <vector>
+
+struct topk_ctx {
+    int device;
+    uint64_t seed;
+    int64_t s_target, c_num, t_fin, r_max, r_fast, band_div, tail_max, timing;
+    // batched form: sample size of a long row, pivot spread, workgroups per CU,
+    // sampling attempts before the exact fallback
+    int64_t bt_s_target, bt_c_num, bt_wg_per_cu, bt_attempts;
+    int num_cu;
+    // kernel timing: event pairs recorded by calls since the last read-out
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_kind;
+    int ev_used = 0;
+    // batched form: instantiated graphs by call arguments
+    hipStream_t capture_stream = nullptr;
+    std::map<std::vector<uint64_t>, hipGraphExec_t> graphs;
+};

@@ -39,26 +39,6 @@ struct Smem {
 };
 
 // ---------------------------------------------------------------------------
-// Pivot ranks (§2, FR-selection: sample ranks k|S|/n -/+ Delta).  Integer form
-// of Delta = ceil(c sqrt(m_hi (s - m_lo) / s)) + 1 with c = c_num / 4:
-// the least D with 16 s D^2 >= c_num^2 m_hi (s - m_lo).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void pivot_ranks(u64 s, u64 k, u64 n, u32 c_num, i64 &lo, i64 &hi)
-{
-    if (s == 0) { lo = -1; hi = 0; return; }
-    const u64 m_lo = k * s / n;
-    const u64 m_hi = (k * s + n - 1) / n;
-    const u64 X = (u64)c_num * c_num * m_hi * (s - m_lo);
-    const u64 Y = 16 * s;
-    const u64 t = (X + Y - 1) / Y;
-    u64 d = (u64)sqrt((double)t);
-    while (d * d < t) ++d;
-    while (d > 0 && (d - 1) * (d - 1) >= t) --d;
-    lo = (i64)m_lo - (i64)(d + 1);
-    hi = (i64)m_hi + (i64)(d + 1);
-}
-
-// ---------------------------------------------------------------------------
 // Sample drawn while a round's middle part b is formed (§2, "Bernoulli
 // sampling": each object independently with probability rho).  Element x
 // (input position) is taken iff word 0 of Philox4x32-10 at counter

@@ -1,0 +1,144 @@
+"""GPU parity of the batched selection (many rows, each with its own k).
+
+Every row's selected set, k-th column and k-th key bits must equal the plain
+oracle's (full sort by (value, column)); the full-size batch is checked row
+by row with the oracle's O(n) checker and sampled rows against the sort.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+tk = pytest.importorskip("paper_1502_03942_amd")
+
+
+def to_dev(keys, off, kk, dev):
+    return (torch.from_numpy(keys).to(dev), torch.from_numpy(off.astype(np.int64)).to(dev),
+            torch.from_numpy(kk.astype(np.int32)).to(dev))
+
+
+def fetch(res):
+    torch.cuda.synchronize()
+    return (res["idx"].cpu().numpy().view(np.uint32), res["kth_idx"].cpu().numpy().view(np.uint32),
+            res["kth_key"].cpu().numpy().view(np.uint32), int(res["status"].item()),
+            res["out_off"].cpu().numpy())
+
+
+def check_rows(keys, off, kk, res, largest, rows=None, full=True):
+    idx, kth, kkey, status, oo = fetch(res)
+    assert status == 0
+    R = len(kk)
+    for r in (range(R) if rows is None else rows):
+        row = keys[int(off[r]):int(off[r + 1])]
+        k = int(kk[r])
+        sel = idx[int(oo[r]):int(oo[r]) + k]
+        assert oracle.check(row, k, sel, int(kth[r]), int(kkey[r]), largest) == 0, r
+        if full:
+            ref = oracle.select_sort(row, k, largest=largest)
+            assert np.array_equal(np.sort(sel), np.sort(ref)), r
+            assert int(kth[r]) == int(ref[-1]), r
+
+
+def ragged(lens, ks, gen):
+    off = np.zeros(len(lens) + 1, np.uint64)
+    off[1:] = np.cumsum(lens)
+    keys = gen(int(off[-1]))
+    return keys, off, np.array(ks, np.uint32)
+
+
+MIXED_LENS = [1, 2, 63, 64, 1000, 4095, 4096, 4097, 5000, 8192, 20000, 65537, 150000, 300001]
+
+
+def mixed_ks(lens, rng):
+    out = []
+    for L in lens:
+        out.append([1, L, min(L, 2048), int(rng.integers(1, L + 1))][int(rng.integers(0, 4))])
+    return out
+
+
+@pytest.mark.parametrize("largest", [False, True])
+@pytest.mark.parametrize("dist", ["normal", "specials", "alphabet"])
+def test_batched_mixed(dev, largest, dist):
+    rng = np.random.default_rng(21)
+    lens = MIXED_LENS * 2
+    ks = mixed_ks(lens, rng)
+    gens = {
+        "normal": lambda n: synth.normal_f32(n, 22),
+        "specials": lambda n: synth.specials_f32(n, 23),
+        "alphabet": lambda n: np.random.default_rng(24).integers(0, 5, n).astype(np.float32),
+    }
+    keys, off, kk = ragged(lens, ks, gens[dist])
+    ctx = tk.Context(0, seed=7)
+    res = ctx.select_batched(*to_dev(keys, off, kk, dev), largest=largest)
+    check_rows(keys, off, kk, res, largest)
+
+
+def test_batched_every_k_small_rows(dev):
+    lens = [37] * 37
+    ks = list(range(1, 38))
+    keys, off, kk = ragged(lens, ks, lambda n: synth.normal_f32(n, 25))
+    ctx = tk.Context(0)
+    res = ctx.select_batched(*to_dev(keys, off, kk, dev))
+    check_rows(keys, off, kk, res, False)
+
+
+def test_batched_exact_fallback(dev):
+    # one sampling attempt with a tiny spread: most long rows miss and the
+    # exact radix fallback over the row produces the result
+    rng = np.random.default_rng(26)
+    lens = [20000, 70000, 300000, 5000, 100000]
+    ks = [int(rng.integers(1, min(L, 2048) + 1)) for L in lens]
+    keys, off, kk = ragged(lens, ks, lambda n: synth.normal_f32(n, 27))
+    ctx = tk.Context(0, seed=3)
+    ctx.set_param("bt_attempts", 1).set_param("bt_c_num", 4).set_param("bt_s_target", 64)
+    res = ctx.select_batched(*to_dev(keys, off, kk, dev))
+    check_rows(keys, off, kk, res, False)
+
+
+def test_batched_graph_replay(dev):
+    rng = np.random.default_rng(28)
+    lens = MIXED_LENS
+    ks = mixed_ks(lens, rng)
+    keys, off, kk = ragged(lens, ks, lambda n: synth.normal_f32(n, 29))
+    kd, od, kd2 = to_dev(keys, off, kk, dev)
+    ctx = tk.Context(0, seed=5)
+    eager = ctx.select_batched(kd, od, kd2)
+    e = fetch(eager)
+    out = None
+    for rep in range(3):
+        out = ctx.select_batched(kd, od, kd2, graph=True, out=out)
+        g = fetch(out)
+        assert all(np.array_equal(a, b) for a, b in zip(e[:3], g[:3])) and g[3] == 0, rep
+        torch.randn(1 << 20, device=dev).sum()      # unrelated eager work between replays
+    # the graph reads the keys each replay: change them in place
+    keys2 = synth.normal_f32(keys.size, 30)
+    kd.copy_(torch.from_numpy(keys2).to(dev))
+    out = ctx.select_batched(kd, od, kd2, graph=True, out=out)
+    check_rows(keys2, off, kk, out, False)
+
+
+def test_batched_bad_rows(dev):
+    lens = [100, 100, 100, 0]
+    ks = [10, 0, 101, 0]
+    keys, off, kk = ragged(lens, ks, lambda n: synth.normal_f32(n, 31))
+    ctx = tk.Context(0)
+    res = ctx.select_batched(*to_dev(keys, off, kk, dev))
+    idx, kth, kkey, status, oo = fetch(res)
+    assert status == tk.STATUS_BAD_ROW
+    ref = oracle.select_sort(keys[:100], 10)
+    assert np.array_equal(np.sort(idx[:10]), np.sort(ref)) and int(kth[0]) == int(ref[-1])
+
+
+def test_batched_fullsize(dev):
+    keys, off, kk = synth.lognormal_rows(65536, 4096, 1.0, 64, 1 << 20, 2048, 4)
+    ctx = tk.Context(0)
+    res = ctx.select_batched(*to_dev(keys, off, kk, dev), graph=True)
+    lens = np.diff(off.astype(np.int64))
+    longest = np.argsort(-lens)[:8].tolist()
+    sample = sorted(set(longest + list(range(0, 65536, 997))))
+    check_rows(keys, off, kk, res, False, rows=sample, full=True)
+    check_rows(keys, off, kk, res, False, full=False)
