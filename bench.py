@@ -188,6 +188,103 @@ def bench_select(args):
     }
 
 
+def bench_batched(args):
+    """The batched form on 65,536 lognormal rows (one graph launch per step),
+    next to the plain per-row loop (topk_select_f32 per row) on a sample of
+    rows, scaled to the whole batch."""
+    import torch
+    import paper_1502_03942_amd as tk
+    import synth
+
+    dev = torch.device("cuda:0")
+    R = 65536
+    log("generating the batch (%d rows)" % R)
+    keys_np, off_np, k_np = synth.lognormal_rows(R, 4096, 1.0, 64, 1 << 20, 2048, 4)
+    keys = torch.from_numpy(keys_np).to(dev)
+    off = torch.from_numpy(off_np.astype(np.int64)).to(dev)
+    kk = torch.from_numpy(k_np.astype(np.int32)).to(dev)
+    ctx = tk.Context(0, seed=0x5EED)
+    out = ctx.select_batched(keys, off, kk, graph=True)
+    for _ in range(max(1, args.warmup)):
+        out = ctx.select_batched(keys, off, kk, graph=True, out=out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    steps = max(1, args.steps)
+    e0.record(stream)
+    for _ in range(steps):
+        out = ctx.select_batched(keys, off, kk, graph=True, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    if int(out["status"].item()) != 0:
+        raise SystemExit("batched status %d" % int(out["status"].item()))
+    total = int(off_np[-1])
+    sum_k = int(k_np.astype(np.int64).sum())
+    b_min = 4 * total + 4 * sum_k + 20 * R
+    # plain per-row loop on a sample of rows (every 64th row), scaled by rows
+    lens = np.diff(off_np.astype(np.int64))
+    rows = list(range(0, R, 64))
+    ws = ctx.workspace(int(lens.max()))
+    for r in rows[:8]:
+        ctx.select(keys[int(off_np[r]):int(off_np[r + 1])], int(k_np[r]), workspace=ws)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for r in rows:
+        ctx.select(keys[int(off_np[r]):int(off_np[r + 1])], int(k_np[r]), workspace=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    loop_ms = e0.elapsed_time(e1) * R / len(rows)
+    log("batched: %.3f ms, per-row loop (scaled from %d rows): %.1f ms" % (ms, len(rows), loop_ms))
+    return {"workload": "65,536 rows f32 ~N(0,1), lengths lognormal (median 4096, sigma 1, "
+                        "clipped to [64, 2^20]), k ~ U{1..min(len, 2048)}, seed 4; one hipGraph "
+                        "launch per step",
+            "rows": R, "keys": total, "sum_k": sum_k, "ms": round(ms, 4),
+            "gkeys_s": round(total / (ms * 1e-3) / 1e9, 2),
+            "hbm_frac_min_bytes": round(b_min / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "per_row_loop": {"ms_est": round(loop_ms, 2), "rows_timed": len(rows),
+                             "how": "topk_select_f32 per row on the same stream, every 64th "
+                                    "row, time scaled by 64",
+                             "speedup": round(loop_ms / ms, 1)}}
+
+
+def bench_rows(args):
+    """Row-wise top-k forward and gradient scatter, scores [4096, 32768], k = 64."""
+    import torch
+    import paper_1502_03942_amd as tk
+
+    dev = torch.device("cuda:0")
+    B, N, k = 4096, 32768, 64
+    g = torch.Generator(device="cpu").manual_seed(5)
+    scores = torch.randn(B, N, generator=g).to(dev)
+    gout = torch.randn(B, k, generator=g).to(dev)
+    v, i = tk.rows_fwd(scores, k)
+    gin = tk.scatter_bwd(gout, i, N)
+    stream = torch.cuda.current_stream(dev)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    steps = max(1, args.steps)
+    torch.cuda.synchronize()
+    e[0].record(stream)
+    for _ in range(steps):
+        v, i = tk.rows_fwd(scores, k)
+    e[1].record(stream)
+    for _ in range(steps):
+        gin = tk.scatter_bwd(gout, i, N)
+    e[2].record(stream)
+    torch.cuda.synchronize()
+    fwd = e[0].elapsed_time(e[1]) / steps
+    bwd = e[1].elapsed_time(e[2]) / steps
+    fb = 4 * B * N + 12 * B * k
+    bb = 4 * B * N + 12 * B * k
+    return {"workload": "scores f32 [4096, 32768] ~N(0,1) seed 5, k = 64 largest; grad_out "
+                        "f32 [4096, 64]",
+            "fwd_ms": round(fwd, 4), "fwd_gbs": round(fb / (fwd * 1e-3) / 1e9, 1),
+            "fwd_frac": round(fb / (fwd * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "bwd_ms": round(bwd, 4), "bwd_gbs": round(bb / (bwd * 1e-3) / 1e9, 1),
+            "bwd_frac": round(bb / (bwd * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,6 +292,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--single-only", action="store_true",
+                    help="only the single-instance selection (skip the batched and row forms)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (the reference kernel "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -212,6 +311,9 @@ def main():
         log("copy calibration: 2^30 bytes read, 2^30 bytes written")
         del src, dst
     out = bench_select(args)
+    if not args.single_only:
+        out["batched"] = bench_batched(args)
+        out["rows_topk"] = bench_rows(args)
     print(json.dumps(out), flush=True)
 
 
