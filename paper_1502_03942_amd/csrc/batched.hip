@@ -2,8 +2,8 @@
 // persistent launch (§1: many similar selections solved together).
 //
 // Rows are ordered longest first (a counting sort by floor(log2 len)) and
-// taken round-robin by a persistent grid of 256-thread workgroups, so no row
-// needs an atomic.  One workgroup solves a row by the sampling method of §2
+// handed out from a queue to a persistent grid of 256-thread workgroups: one
+// row per grab for the long rows, 16 per grab afterwards.  One workgroup solves a row by the sampling method of §2
 // with the workgroup as the machine:
 //   - a row of at most BT_CAP keys is the base case: its (ord, column) pairs go
 //     to LDS and the pair of rank k is found exactly;
@@ -43,14 +43,18 @@ constexpr int BT_IPT = 16;                      // keys per thread per sweep ste
 constexpr u32 BT_STEP = BT_THREADS * BT_IPT;
 constexpr int BT_NCLS = 34;                     // length classes 0 (empty) .. 33
 constexpr int BT_HIST_THREADS = 1024;
+constexpr u32 BT_Q1 = 4096;                     // queue: rows taken one at a time first
+constexpr u32 BT_QCHUNK = 16;                   // then this many per grab
 
 struct BtShared {
     u64 buf[BT_CAP];
-    u32 hist[BT_BINS];
-    u64 cand[WAVE];
-    u64 rmin, rmax, found;
-    u32 ccount, sel_bin, sel_before, sel_count;
+    u32 hist[BT_BINS];          // two targets' counts packed (low / high 16 bits)
+    u64 cand[2][WAVE];
+    u64 rmin[2], rmax[2], found[2];
+    u32 ccount[2], sel_bin[2], sel_before[2], sel_count[2];
     u32 scan[BT_WAVES];
+    u32 wt[2][BT_WAVES];        // sweep: per-wave (|a| | |b| << 16) of a step, by step parity
+    u32 next;                   // next row position handed to this workgroup
 };
 
 struct BtArgs {
@@ -60,7 +64,7 @@ struct BtArgs {
     const u64 *out_off;
     u32 rows, flags;
     u32 *out_idx, *kth_key, *kth_idx, *status;
-    u32 *cls_cnt, *cls_fill, *order;
+    u32 *cls_cnt, *cls_fill, *order, *queue;
     u64 seed;
     u32 s_target, c_num, attempts;
 };
@@ -76,53 +80,57 @@ __device__ __forceinline__ bool bt_match(u64 x, u64 pref, int lowb)
     return lowb >= 64 || (x >> lowb) == (pref >> lowb);
 }
 
-// Pair of 0-based rank `rank` among src(0 .. n-1) (distinct pairs): radix
-// select over the RS-style adaptive window below the common prefix of the
-// candidates' minimum and maximum; a bucket of at most 64 is ranked by one
-// wave.  All threads call it and get the result.
+// Pairs of 0-based ranks rank[0], rank[1] (each if act[t]) among src(0 .. n-1)
+// (distinct pairs): radix select over windows of BT_BITS bits, from bit `top`
+// down (every pair agrees above `top`), keeping the bucket that holds each
+// rank; a bucket of at most 64 pairs is ranked by one wave.  Both targets
+// share every scan of the source; their counts share one histogram (16 bits
+// each) when n < 2^16, else only target 0 may be active.  All threads call it
+// and get res[].
 template <class SRC>
-__device__ u64 bt_select(SRC src, u32 n, u64 rank, BtShared &sh)
+__device__ void bt_select(SRC src, u32 n, int top, const u64 rank_in[2], const bool act[2],
+                          u64 res[2], BtShared &sh)
 {
     const u32 tid = threadIdx.x, lane = lane_id();
     const u32 w = __builtin_amdgcn_readfirstlane(tid / WAVE);
-    u64 pref = 0;
-    int lowb = 64;
+    const bool packed = n < 65536u;
+    u64 pref[2] = {0ull, 0ull};
+    int lowb[2] = {top, top};           // bits [lowb, 64) of the candidates equal pref's
+    u64 rank[2] = {rank_in[0], rank_in[1]};
+    bool done[2] = {!act[0], !act[1]};
+    res[0] = res[1] = 0ull;
     for (u32 i = tid; i < BT_BINS; i += BT_THREADS) sh.hist[i] = 0u;
-    for (int pass = 0; pass < 16; ++pass) {
-        if (tid == 0) {
-            sh.rmin = ~0ull;
-            sh.rmax = 0ull;
-            sh.ccount = 0u;
-        }
-        __syncthreads();
-        u64 mn = ~0ull, mx = 0ull;
-        for (u32 i = tid; i < n; i += BT_THREADS) {
-            const u64 x = src(i);
-            if (bt_match(x, pref, lowb)) {
-                mn = x < mn ? x : mn;
-                mx = x > mx ? x : mx;
+    if (tid < 2) sh.ccount[tid] = 0u;
+    if (top >= 64) {
+        // pref's bits at or above `top` are those of any pair
+        const u64 x0 = n ? src(0) : 0ull;
+        pref[0] = pref[1] = x0;
+    } else {
+        const u64 x0 = n ? src(0) : 0ull;
+        pref[0] = pref[1] = top <= 0 ? x0 : (x0 >> top) << top;
+    }
+    __syncthreads();
+    for (int pass = 0; pass < 16 && !(done[0] && done[1]); ++pass) {
+        int sh_[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            if (!done[t] && lowb[t] <= 0) {
+                res[t] = pref[t];                   // every bit fixed: one pair
+                done[t] = true;
             }
+            sh_[t] = lowb[t] > BT_BITS ? lowb[t] - BT_BITS : 0;
         }
-        mn = wave_min_u64(mn);
-        mx = wave_max_u64(mx);
-        if (lane == 0 && mn <= mx) {
-            atomicMin((unsigned long long *)&sh.rmin, (unsigned long long)mn);
-            atomicMax((unsigned long long *)&sh.rmax, (unsigned long long)mx);
-        }
-        __syncthreads();
-        const u64 gmn = sh.rmin, gmx = sh.rmax;
-        if (gmn == gmx) {
-            __syncthreads();            // everyone has read them before the next use
-            return gmn;
-        }
-        const int hb = 63 - __clzll((long long)(gmn ^ gmx));
-        const int sh_ = hb >= BT_BITS - 1 ? hb - (BT_BITS - 1) : 0;
+        if (done[0] && done[1]) break;
+        // (1) histogram of each target's window
         for (u32 i = tid; i < n; i += BT_THREADS) {
             const u64 x = src(i);
-            if (bt_match(x, pref, lowb)) atomicAdd(&sh.hist[(u32)(x >> sh_) & (BT_BINS - 1)], 1u);
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                if (!done[t] && bt_match(x, pref[t], lowb[t]))
+                    atomicAdd(&sh.hist[(u32)(x >> sh_[t]) & (BT_BINS - 1)], t == 0 ? 1u : 65536u);
         }
         __syncthreads();
-        // thread t covers bins [8t, 8t + 8)
+        // (2) scan: thread t covers bins [8t, 8t + 8)
         u32 c[8], csum = 0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -134,27 +142,52 @@ __device__ u64 bt_select(SRC src, u32 n, u64 rank, BtShared &sh)
         u32 before = block_excl_scan<BT_THREADS>(csum, sh.scan, &tot);
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            if ((u64)before <= rank && rank < (u64)before + c[q]) {
-                sh.sel_bin = tid * 8 + q;
-                sh.sel_before = before;
-                sh.sel_count = c[q];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                if (done[t]) continue;
+                const u32 bt = !packed ? before : t == 0 ? (before & 0xFFFFu) : (before >> 16);
+                const u32 ct = !packed ? c[q] : t == 0 ? (c[q] & 0xFFFFu) : (c[q] >> 16);
+                if ((u64)bt <= rank[t] && rank[t] < (u64)bt + ct) {
+                    sh.sel_bin[t] = tid * 8 + q;
+                    sh.sel_before[t] = bt;
+                    sh.sel_count[t] = ct;
+                }
             }
             before += c[q];
         }
         __syncthreads();
-        const int top = sh_ + BT_BITS;
-        pref = (top >= 64 ? 0ull : (gmn >> top) << top) | ((u64)sh.sel_bin << sh_);
-        lowb = sh_;
-        rank -= sh.sel_before;
-        if (sh.sel_count <= (u32)WAVE) {
+        bool gather[2] = {false, false};
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            if (done[t]) continue;
+            const u32 wb = lowb[t] - sh_[t];                    // window width
+            const u64 wmask = wb >= 64 ? ~0ull : ((1ull << wb) - 1) << sh_[t];
+            pref[t] = (pref[t] & ~wmask) | (((u64)sh.sel_bin[t] << sh_[t]) & wmask);
+            lowb[t] = sh_[t];
+            rank[t] -= sh.sel_before[t];
+            if (sh.sel_count[t] == 1u || lowb[t] == 0) {
+                if (lowb[t] == 0) {
+                    res[t] = pref[t];                           // every bit fixed
+                    done[t] = true;
+                } else {
+                    gather[t] = true;
+                }
+            } else {
+                gather[t] = sh.sel_count[t] <= (u32)WAVE;
+            }
+        }
+        if (gather[0] || gather[1]) {
             for (u32 i = tid; i < n; i += BT_THREADS) {
                 const u64 x = src(i);
-                if (bt_match(x, pref, lowb)) sh.cand[atomicAdd(&sh.ccount, 1u)] = x;
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+                    if (gather[t] && bt_match(x, pref[t], lowb[t]))
+                        sh.cand[t][atomicAdd(&sh.ccount[t], 1u)] = x;
             }
             __syncthreads();
-            if (w == 0) {
-                const u32 m = sh.ccount;
-                const u64 mine = lane < m ? sh.cand[lane] : ~0ull;
+            if (w < 2 && gather[w]) {
+                const u32 m = sh.ccount[w];
+                const u64 mine = lane < m ? sh.cand[w][lane] : ~0ull;
                 const u32 mlo = (u32)mine, mhi = (u32)(mine >> 32);
                 u32 below = 0;
                 for (u32 i = 0; i < m; ++i) {
@@ -162,15 +195,19 @@ __device__ u64 bt_select(SRC src, u32 n, u64 rank, BtShared &sh)
                                   (u32)__builtin_amdgcn_readlane((int)mlo, (int)i);
                     below += o < mine ? 1u : 0u;
                 }
-                if (lane < m && (u64)below == rank) sh.found = mine;
+                if (lane < m && (u64)below == rank[w]) sh.found[w] = mine;
             }
             __syncthreads();
-            const u64 f = sh.found;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                if (!gather[t]) continue;
+                res[t] = sh.found[t];
+                done[t] = true;
+            }
+            if (tid < 2) sh.ccount[tid] = 0u;
             __syncthreads();
-            return f;
         }
     }
-    return sh.found;
 }
 
 // Write the columns of the pairs <= tau among src(0 .. n-1), in source order,
@@ -207,36 +244,33 @@ __device__ void bt_emit(SRC src, u32 n, u64 tau, u32 *out, u32 limit, BtShared &
 // Geometric-skip Bernoulli sample of a row (rate s_target / len): thread t
 // samples its segment [t L, min(t L + L, len)), L = ceil(len / 256), with
 // skips 1 + floor(ln U / ln(1 - rho)), U from Philox4x32-10 at counter
-// (j / 4, t, tag, row), key = seed; at most BT_SEG per segment.
+// (j / 4, t, tag, row), key = seed; at most BT_SEG per segment.  The skips of
+// a segment are independent, so they are evaluated together (fp32: the
+// sample only guides the pivots) and summed.
 __device__ __forceinline__ int bt_sample(u32 t, u64 len, u32 s_target, u64 seed, u32 tag,
                                          u32 row, u32 (&pos)[BT_SEG])
 {
-    const double rho = (double)s_target / (double)len;
+    const float rho = (float)s_target / (float)len;
     const u64 L = (len + BT_THREADS - 1) / BT_THREADS;
     const u64 s0 = (u64)t * L;
     const u64 e0 = s0 + L < len ? s0 + L : len;
     if (s0 >= e0) return 0;
-    const double ln1mrho = log1p(-rho);
-    i64 p = (i64)s0 - 1;
+    const float inv = 1.0f / log1pf(-rho);
+    u32 w[BT_SEG];
+#pragma unroll
+    for (int j = 0; j < BT_SEG; j += 4) {
+        const uint4 r4 = philox4x32_10(make_uint4((u32)(j >> 2), t, tag, row), (u32)seed, (u32)(seed >> 32));
+        w[j] = r4.x; w[j + 1] = r4.y; w[j + 2] = r4.z; w[j + 3] = r4.w;
+    }
+    u64 p = s0 - 1;
     int cnt = 0;
-    bool stop = false;
-    uint4 r4 = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
     for (int j = 0; j < BT_SEG; ++j) {
-        if (!stop) {
-            if ((j & 3) == 0)
-                r4 = philox4x32_10(make_uint4((u32)(j >> 2), t, tag, row), (u32)seed, (u32)(seed >> 32));
-            const u32 w = (j & 3) == 0 ? r4.x : (j & 3) == 1 ? r4.y : (j & 3) == 2 ? r4.z : r4.w;
-            const double u = ((double)w + 0.5) * (1.0 / 4294967296.0);
-            const double q = log(u) / ln1mrho;
-            if (q >= (double)((i64)e0 - 1 - p)) {
-                stop = true;
-            } else {
-                p = p + 1 + (i64)q;
-                pos[j] = (u32)p;
-                cnt = j + 1;
-            }
-        }
+        const float u = ((float)(w[j] >> 8) + 0.5f) * (1.0f / 16777216.0f);
+        const float q = __logf(u) * inv;
+        const u64 skip = q >= (float)L ? L + 1 : 1 + (u64)q;
+        p += skip;
+        if (p < e0) { pos[j] = (u32)p; cnt = j + 1; }
     }
     return cnt;
 }
@@ -260,8 +294,19 @@ __device__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
 
     u32 na = 0, nb = len;
     bool in_lds = false;
+    int band_top = 64;                  // pairs in LDS agree at and above this bit
     if (len <= BT_CAP) {
-        for (u32 i = tid; i < len; i += BT_THREADS) sh.buf[i] = gsrc(i);
+        u32 x[BT_CAP / BT_THREADS];                // all loads first, one wait
+#pragma unroll
+        for (int j = 0; j < (int)(BT_CAP / BT_THREADS); ++j) {
+            const u32 i = (u32)j * BT_THREADS + tid;
+            x[j] = i < len ? row[i] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < (int)(BT_CAP / BT_THREADS); ++j) {
+            const u32 i = (u32)j * BT_THREADS + tid;
+            if (i < len) sh.buf[i] = pack(key_ord<true, LARGEST>(x[j]), i);
+        }
         __syncthreads();
         in_lds = true;
     } else {
@@ -279,39 +324,74 @@ __device__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
             i64 lo, hi;
             pivot_ranks(s, k, len, c_num, lo, hi);
             const bool hl = lo >= 0, hr = hi < (i64)s;
-            const u64 L = hl ? bt_select(lsrc, s, (u64)lo, sh) : 0ull;
-            const u64 R = hr ? bt_select(lsrc, s, (u64)hi, sh) : ~0ull;
-            // one sweep: below L -> output, [L, R] -> LDS band
+            u64 piv[2];
+            {
+                const u64 rk[2] = {hl ? (u64)lo : 0ull, hr ? (u64)hi : 0ull};
+                const bool ac[2] = {hl, hr};
+                bt_select(lsrc, s, 64, rk, ac, piv, sh);
+            }
+            const u64 L = hl ? piv[0] : 0ull;
+            const u64 R = hr ? piv[1] : ~0ull;
+            // one sweep: below L -> output, [L, R] -> LDS band.  Wave w takes
+            // keys [s0 + 1024 w, s0 + 1024 w + 1024) of a step as 16 columns of
+            // 64 lanes (coalesced); lane bits keep its keys' parts; the waves'
+            // counts are exchanged once per step.
             u32 ca = 0, cb = 0;
-            for (u32 s0 = 0; s0 < len; s0 += BT_STEP) {
-                u64 v[BT_IPT];
-                u32 ta = 0, tb = 0;
+            {
+                const u32 wv = __builtin_amdgcn_readfirstlane(tid / WAVE), ln = lane_id();
+                for (u32 s0 = 0, st = 0; s0 < len; s0 += BT_STEP, ++st) {
+                    const u32 base = s0 + wv * (BT_STEP / BT_WAVES);
+                    u32 o[16];
 #pragma unroll
-                for (int j = 0; j < BT_IPT; ++j) {
-                    const u32 i = s0 + tid * BT_IPT + (u32)j;
-                    v[j] = i < len ? gsrc(i) : ~0ull;
-                    const bool inb = i < len && !(hl && v[j] < L) && !(hr && v[j] > R);
-                    ta += (i < len && hl && v[j] < L) ? 1u : 0u;
-                    tb += inb ? 1u : 0u;
-                }
-                u32 tot;
-                const u32 ex = block_excl_scan<BT_THREADS>(ta | (tb << 16), sh.scan, &tot);
-                u32 pa = ca + (ex & 0xFFFFu), pb = cb + (ex >> 16);
+                    for (int j = 0; j < 16; ++j) {
+                        const u32 col = base + (u32)j * WAVE + ln;
+                        o[j] = col < len ? row[col] : 0u;
+                    }
+                    u32 abits = 0, bbits = 0, ta = 0, tb = 0;
 #pragma unroll
-                for (int j = 0; j < BT_IPT; ++j) {
-                    const u32 i = s0 + tid * BT_IPT + (u32)j;
-                    if (i < len) {
-                        if (hl && v[j] < L) {
-                            if (pa < k) out[pa] = i;
-                            ++pa;
-                        } else if (!(hr && v[j] > R)) {
-                            if (pb < BT_CAP) sh.buf[pb] = v[j];
-                            ++pb;
+                    for (int j = 0; j < 16; ++j) {
+                        const u32 col = base + (u32)j * WAVE + ln;
+                        o[j] = key_ord<true, LARGEST>(o[j]);
+                        const u64 c = pack(o[j], col);
+                        const bool ok = col < len;
+                        const bool ia = ok && hl && c < L;
+                        const bool ib = ok && !(hl && c < L) && !(hr && c > R);
+                        abits |= (u32)ia << j;
+                        bbits |= (u32)ib << j;
+                        ta += (u32)__popcll(ballot(ia));
+                        tb += (u32)__popcll(ballot(ib));
+                        asm volatile("" : "+s"(ta), "+s"(tb));   // keep the sums current
+                    }
+                    const u32 par = st & 1u;
+                    if (ln == 0) sh.wt[par][wv] = ta | (tb << 16);
+                    __syncthreads();
+                    u32 pa = ca, pb = cb, sa = 0, sb = 0;
+#pragma unroll
+                    for (int v = 0; v < BT_WAVES; ++v) {
+                        const u32 x = sh.wt[par][v];
+                        if ((u32)v < wv) { pa += x & 0xFFFFu; pb += x >> 16; }
+                        sa += x & 0xFFFFu;
+                        sb += x >> 16;
+                    }
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) {
+                        const u32 col = base + (u32)j * WAVE + ln;
+                        const bool ia = (abits >> j) & 1u, ib = (bbits >> j) & 1u;
+                        const u64 ma = ballot(ia), mb = ballot(ib);
+                        if (ma) {
+                            const u32 q = pa + mbcnt(ma);
+                            if (ia && q < k) out[q] = col;
+                            pa += (u32)__popcll(ma);
+                        }
+                        if (mb) {
+                            const u32 q = pb + mbcnt(mb);
+                            if (ib && q < BT_CAP) sh.buf[q] = pack(o[j], col);
+                            pb += (u32)__popcll(mb);
                         }
                     }
+                    ca += sa;
+                    cb += sb;
                 }
-                ca += tot & 0xFFFFu;
-                cb += tot >> 16;
             }
             __syncthreads();
             if (ca >= k || ca + cb < k) {
@@ -322,16 +402,25 @@ __device__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
                 na = ca;
                 nb = cb;
                 in_lds = true;
+                // every band pair lies in [L, R]: they agree above the highest
+                // bit in which L and R differ
+                if (hl && hr) band_top = (L == R) ? 0 : 64 - __clzll((long long)(L ^ R));
             }
         }
     }
     u64 tau;
+    const bool one[2] = {true, false};
+    u64 t2[2];
     if (in_lds) {
-        tau = bt_select(lsrc, nb, (u64)(k - na - 1), sh);
+        const u64 rk[2] = {(u64)(k - na - 1), 0ull};
+        bt_select(lsrc, nb, band_top, rk, one, t2, sh);
+        tau = t2[0];
         bt_emit(lsrc, nb, tau, out + na, k - na, sh);
     } else {
         // exact fallback over the row
-        tau = bt_select(gsrc, len, (u64)(k - 1), sh);
+        const u64 rk[2] = {(u64)(k - 1), 0ull};
+        bt_select(gsrc, len, 64, rk, one, t2, sh);
+        tau = t2[0];
         bt_emit(gsrc, len, tau, out, k, sh);
     }
     if (tid == 0) {
@@ -345,7 +434,18 @@ template <bool LARGEST>
 __global__ __launch_bounds__(BT_THREADS) void k_batched(BtArgs a)
 {
     __shared__ BtShared sh;
-    for (u32 p = blockIdx.x; p < a.rows; p += gridDim.x) bt_row<LARGEST>(a, a.order[p], sh);
+    // rows in longest-first order from a queue: one row per grab for the first
+    // BT_Q1 positions (the long rows), then BT_QCHUNK rows per grab
+    for (;;) {
+        if (threadIdx.x == 0) sh.next = atomicAdd(a.queue, 1u);
+        __syncthreads();
+        const u32 g = sh.next;
+        __syncthreads();
+        const u32 p0 = g < BT_Q1 ? g : BT_Q1 + (g - BT_Q1) * BT_QCHUNK;
+        if (p0 >= a.rows) break;
+        const u32 p1 = g < BT_Q1 ? p0 + 1 : (p0 + BT_QCHUNK < a.rows ? p0 + BT_QCHUNK : a.rows);
+        for (u32 p = p0; p < p1; ++p) bt_row<LARGEST>(a, a.order[p], sh);
+    }
 }
 
 // Zero the class counters and the status word (a kernel, so the call can be
@@ -357,7 +457,10 @@ __global__ void k_bt_init(BtArgs a)
         a.cls_cnt[t] = 0u;
         a.cls_fill[t] = 0u;
     }
-    if (t == 0) *a.status = 0u;
+    if (t == 0) {
+        *a.status = 0u;
+        *a.queue = 0u;
+    }
 }
 
 // Rows per length class (workgroup histogram, one global add per class).
@@ -406,7 +509,7 @@ constexpr size_t BT_ALIGN = 256;
 inline size_t bt_align(size_t x) { return (x + BT_ALIGN - 1) / BT_ALIGN * BT_ALIGN; }
 
 struct BtLayout {
-    size_t cnt, fill, order, total;
+    size_t cnt, fill, queue, order, total;
 };
 
 BtLayout bt_layout(uint32_t rows)
@@ -417,6 +520,8 @@ BtLayout bt_layout(uint32_t rows)
     off = bt_align(off + BT_NCLS * sizeof(uint32_t));
     L.fill = off;
     off = bt_align(off + BT_NCLS * sizeof(uint32_t));
+    L.queue = off;
+    off = bt_align(off + 128);
     L.order = off;
     off = bt_align(off + (size_t)rows * sizeof(uint32_t));
     L.total = off;
@@ -476,6 +581,7 @@ extern "C" int topk_select_batched_f32(topk_ctx *c, const float *keys, const uin
     a.cls_cnt = (u32 *)(w + L.cnt);
     a.cls_fill = (u32 *)(w + L.fill);
     a.order = (u32 *)(w + L.order);
+    a.queue = (u32 *)(w + L.queue);
     a.seed = c->seed;
     a.s_target = (u32)c->bt_s_target;
     a.c_num = (u32)c->bt_c_num;
