@@ -78,7 +78,7 @@ void topk_destroy(topk_ctx *ctx);
  *   "c_num"      16    pivot spread c = c_num / 4; the pivots are the sample
  *                      elements of rank k s/n -/+ Delta, Delta = ceil(c sqrt(
  *                      m_hi (s - m_lo) / s)) + 1 (§2, FR-selection); 0..4096
- *   "t_fin"      8192  subproblems of at most this size are solved directly
+ *   "t_fin"     16384  subproblems of at most this size are solved directly
  *                      in one workgroup (§2 base case); 1..16384
  *   "r_max"      24    attempt budget (rounds + repeated rounds); 1..32
  *   "r_fast"     -1    multi-workgroup rounds enqueued before the single-

@@ -184,7 +184,7 @@ int topk_create(topk_ctx **out, int hip_device, uint64_t seed)
     c->seed = seed;
     c->s_target = 4096;
     c->c_num = 16;
-    c->t_fin = 8192;
+    c->t_fin = 16384;
     c->r_max = 24;
     c->r_fast = -1;
     c->band_div = 4;
