@@ -36,8 +36,9 @@ namespace topk {
 constexpr int BT_THREADS = 256;                 // 4 waves
 constexpr int BT_WAVES = BT_THREADS / WAVE;
 constexpr u32 BT_CAP = 4096;                    // pairs in LDS: a short row or a band
-constexpr int BT_BITS = 11;                     // radix digit
+constexpr int BT_BITS = 10;                     // radix digit
 constexpr u32 BT_BINS = 1u << BT_BITS;
+constexpr int BT_BPT = (int)BT_BINS / BT_THREADS;   // histogram bins per thread in the scan
 constexpr int BT_SEG = 8;                       // sample slots per thread
 constexpr int BT_IPT = 16;                      // keys per thread per sweep step
 constexpr u32 BT_STEP = BT_THREADS * BT_IPT;
@@ -130,25 +131,25 @@ __device__ void bt_select(SRC src, u32 n, int top, const u64 rank_in[2], const b
                     atomicAdd(&sh.hist[(u32)(x >> sh_[t]) & (BT_BINS - 1)], t == 0 ? 1u : 65536u);
         }
         __syncthreads();
-        // (2) scan: thread t covers bins [8t, 8t + 8)
-        u32 c[8], csum = 0;
+        // (2) scan: thread t covers bins [BT_BPT t, BT_BPT t + BT_BPT)
+        u32 c[BT_BPT], csum = 0;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            c[q] = sh.hist[tid * 8 + q];
-            sh.hist[tid * 8 + q] = 0u;       // clean for the next pass
+        for (int q = 0; q < BT_BPT; ++q) {
+            c[q] = sh.hist[tid * BT_BPT + q];
+            sh.hist[tid * BT_BPT + q] = 0u;      // clean for the next pass
             csum += c[q];
         }
         u32 tot;
         u32 before = block_excl_scan<BT_THREADS>(csum, sh.scan, &tot);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < BT_BPT; ++q) {
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
                 if (done[t]) continue;
                 const u32 bt = !packed ? before : t == 0 ? (before & 0xFFFFu) : (before >> 16);
                 const u32 ct = !packed ? c[q] : t == 0 ? (c[q] & 0xFFFFu) : (c[q] >> 16);
                 if ((u64)bt <= rank[t] && rank[t] < (u64)bt + ct) {
-                    sh.sel_bin[t] = tid * 8 + q;
+                    sh.sel_bin[t] = tid * BT_BPT + q;
                     sh.sel_before[t] = bt;
                     sh.sel_count[t] = ct;
                 }
@@ -431,7 +432,7 @@ __device__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
 }
 
 template <bool LARGEST>
-__global__ __launch_bounds__(BT_THREADS) void k_batched(BtArgs a)
+__global__ __launch_bounds__(BT_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_batched(BtArgs a)
 {
     __shared__ BtShared sh;
     // rows in longest-first order from a queue: one row per grab for the first
@@ -587,7 +588,7 @@ extern "C" int topk_select_batched_f32(topk_ctx *c, const float *keys, const uin
     a.c_num = (u32)c->bt_c_num;
     a.attempts = (u32)c->bt_attempts;
     if (hipSetDevice(c->device) != hipSuccess) return TOPK_E_HIP;
-    const int grid = (int)(c->num_cu * c->bt_wg_per_cu);
+    const int grid = (int)(c->num_cu * c->bt_wg_per_cu);   // 4 fit on a CU (LDS, registers)
     if (!(flags & TOPK_GRAPH))
         return bt_enqueue(a, grid, stream) == hipSuccess ? TOPK_OK : TOPK_E_HIP;
 

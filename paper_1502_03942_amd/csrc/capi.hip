@@ -192,7 +192,7 @@ int topk_create(topk_ctx **out, int hip_device, uint64_t seed)
     c->timing = 0;
     c->bt_s_target = 1024;
     c->bt_c_num = 24;
-    c->bt_wg_per_cu = 3;
+    c->bt_wg_per_cu = 4;
     c->bt_attempts = 4;
     c->num_cu = ncu;
     *out = c;
