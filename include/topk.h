@@ -168,9 +168,10 @@ int topk_kernel_times(topk_ctx *ctx, float *ms, int32_t *kind, uint32_t max, uin
  *   row_off  [rows + 1]       u64 row boundaries (non-decreasing)
  *   k        [rows]           u32, 1 <= k[r] <= row length
  *   out_off  [rows + 1]       u64 exclusive prefix sums of k (caller-computed)
- *   out_idx  [out_off[rows]]  row r's selected columns at out_off[r] .. + k[r]:
- *                             the columns below the row's lower pivot in
- *                             column order, then the rest in column order
+ *   out_idx  [out_off[rows]]  row r's selected columns at out_off[r] .. + k[r],
+ *                             in an order fixed by the inputs, seed and
+ *                             parameters (a short row, or one finished by the
+ *                             exact fallback: column order)
  *   kth_key  [rows]           key of rank k[r] (bits as stored)
  *   kth_idx  [rows]           its column
  *   status   [1]              0, or TOPK_STATUS_BAD_ROW if some row had
@@ -178,8 +179,17 @@ int topk_kernel_times(topk_ctx *ctx, float *ms, int32_t *kind, uint32_t max, uin
  *   workspace >= topk_batched_workspace_bytes(ctx, rows, flags), 256-aligned
  * One persistent launch of 256-thread workgroups over the rows, longest rows
  * first; each row by the sampling method with the workgroup as the machine
- * (batched.hip).  Context parameters "bt_s_target", "bt_c_num",
- * "bt_wg_per_cu", "bt_attempts" tune it.  flags: TOPK_LARGEST, TOPK_GRAPH
+ * (batched.hip).  Context parameters tune it:
+ *   "bt_s_target"  1024  expected sample size of a long row; 64..2048
+ *   "bt_c_num"       24  pivot spread (as c_num above); 4..4096
+ *   "bt_wg_per_cu"    4  resident workgroups per CU of the persistent grid; 1..8
+ *   "bt_attempts"     4  sampling attempts before the exact fallback; 1..16
+ *   "bt_fast"         1  1: a row whose expected candidates (keys up to the
+ *                        upper pivot) fit 0.7 of the workgroup's 4096 LDS
+ *                        slots is swept once into per-wave LDS regions; 0:
+ *                        always the general sweep (lower part straight to
+ *                        out_idx, band to LDS)
+ * flags: TOPK_LARGEST, TOPK_GRAPH
  * (capture the four launches into a hipGraph on first use for this exact
  * argument set and replay it afterwards; the ctx keeps the graph).  All
  * pointers are device pointers; asynchronous on `stream`.  Returns TOPK_OK,

@@ -3,24 +3,34 @@
 //
 // Rows are ordered longest first (a counting sort by floor(log2 len)) and
 // handed out from a queue to a persistent grid of 256-thread workgroups: one
-// row per grab for the long rows, 16 per grab afterwards.  One workgroup solves a row by the sampling method of §2
-// with the workgroup as the machine:
-//   - a row of at most BT_CAP keys is the base case: its (ord, column) pairs go
-//     to LDS and the pair of rank k is found exactly;
+// row per grab for the long rows, 16 per grab afterwards.  One workgroup
+// solves a row by the sampling method of §2 with the workgroup as the
+// machine:
+//   - a row of at most BT_REG_KEYS keys is the base case: its key order words
+//     stay in registers, an exact radix select finds the pair of rank k and
+//     the columns up to it are written in column order;
 //   - a longer row draws a Bernoulli sample of about bt_s_target keys
-//     (geometric skips, one segment per thread), takes the pivots at sample
-//     ranks k s / len -/+ Delta, and sweeps the row once: the part below the
-//     lower pivot goes straight to the output (in column order), the band
-//     between the pivots to LDS.  If the band brackets rank k and fits, the
-//     band is finished like a short row.  Otherwise the round is repeated with
-//     a new sample (spread doubled after a miss, halved after an overflow) and
-//     after bt_attempts rounds an exact radix select over the row finishes it.
-// Every decision compares the composite key (ord, column), the unique order
-// of §2, so the selected set is exactly the oracle's.
+//     (geometric skips, one segment per thread) and takes the pivots L, R at
+//     sample ranks k s / len -/+ Delta.  Then one sweep of the row:
+//       fast form (the keys up to R are expected to fill at most 0.7 of the
+//       LDS): every wave appends the keys <= R of its columns, with the
+//       column, to a region of its own, counting those < L; no barrier until
+//       the end.  The band [L, R] then holds rank k, found by one histogram
+//       over the band's order words, and every candidate up to it is output;
+//       general form: the part below L goes straight to the output, the band
+//       to LDS, and the band is finished like a short row.
+//     A miss (rank k outside the band) repeats the round with a new sample
+//     and the spread doubled, an overflow of the LDS with the spread halved
+//     (fast form: the general sweep of the same pivots); after bt_attempts
+//     rounds an exact radix select over the row finishes it.
+// Every decision is taken in the composite order (ord, column) of §2, or in
+// the float order against a pivot value that is not NaN, which agrees with
+// it, so the selected set is exactly the oracle's.
 //
-// Output per row: out_idx[out_off[r] .. + k) holds the selected columns: those
-// below the lower pivot in column order, then the rest in column order (a row
-// finished directly or by the exact fallback: all in column order);
+// Output per row: out_idx[out_off[r] .. + k) holds the selected columns in an
+// order fixed by the inputs and the seed (short row or exact fallback: column
+// order; general form: the part below L, then the rest, each in column order;
+// fast form: wave by wave, each wave's columns ascending);
 // kth_key[r] / kth_idx[r] the pair of rank k (key bits as stored).
 #include <hip/hip_runtime.h>
 #include <string.h>
@@ -35,7 +45,8 @@ namespace topk {
 
 constexpr int BT_THREADS = 256;                 // 4 waves
 constexpr int BT_WAVES = BT_THREADS / WAVE;
-constexpr u32 BT_CAP = 4096;                    // pairs in LDS: a short row or a band
+constexpr u32 BT_CAP = 4096;                    // pairs in LDS: a band or the candidates
+constexpr u32 BT_REG_KEYS = 8192;              // a short row: held in registers (32 per thread)
 constexpr int BT_BITS = 10;                     // radix digit
 constexpr u32 BT_BINS = 1u << BT_BITS;
 constexpr int BT_BPT = (int)BT_BINS / BT_THREADS;   // histogram bins per thread in the scan
@@ -44,6 +55,8 @@ constexpr int BT_IPT = 16;                      // keys per thread per sweep ste
 constexpr u32 BT_STEP = BT_THREADS * BT_IPT;
 constexpr int BT_NCLS = 34;                     // length classes 0 (empty) .. 33
 constexpr int BT_HIST_THREADS = 1024;
+constexpr u32 BT_REG = BT_CAP / BT_WAVES;       // fast sweep: candidate slots per wave
+constexpr u32 BT_FAST_NUM = 7, BT_FAST_DEN = 10; // fast sweep when expected candidates <= 0.7 BT_CAP
 constexpr u32 BT_Q1 = 4096;                     // queue: rows taken one at a time first
 constexpr u32 BT_QCHUNK = 16;                   // then this many per grab
 
@@ -51,6 +64,7 @@ struct BtShared {
     u64 buf[BT_CAP];
     u32 hist[BT_BINS];          // two targets' counts packed (low / high 16 bits)
     u64 cand[2][WAVE];
+    u32 ecnt[BT_REG_KEYS / BT_THREADS * BT_WAVES];   // short row emit: counts per column block and wave
     u64 rmin[2], rmax[2], found[2];
     u32 ccount[2], sel_bin[2], sel_before[2], sel_count[2];
     u32 scan[BT_WAVES];
@@ -67,13 +81,29 @@ struct BtArgs {
     u32 *out_idx, *kth_key, *kth_idx, *status;
     u32 *cls_cnt, *cls_fill, *order, *queue;
     u64 seed;
-    u32 s_target, c_num, attempts;
+    u32 s_target, c_num, attempts, fast;
 };
 
 __device__ __forceinline__ u32 len_class(u64 len)
 {
     const u32 c = len == 0 ? 0u : 64u - (u32)__clzll((long long)len);
     return c < (u32)BT_NCLS ? c : (u32)BT_NCLS - 1;
+}
+
+// The thread index as a value the compiler cannot see through: what is
+// derived from it is computed where it is used, not hoisted out of the
+// persistent row loop into registers that then spill.
+__device__ __forceinline__ u32 bt_tid()
+{
+    u32 t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
+__device__ __forceinline__ u64 uniform64(u64 x)
+{
+    return ((u64)(u32)__builtin_amdgcn_readfirstlane((u32)(x >> 32)) << 32) |
+           (u32)__builtin_amdgcn_readfirstlane((u32)x);
 }
 
 __device__ __forceinline__ bool bt_match(u64 x, u64 pref, int lowb)
@@ -92,7 +122,7 @@ template <class SRC>
 __device__ void bt_select(SRC src, u32 n, int top, const u64 rank_in[2], const bool act[2],
                           u64 res[2], BtShared &sh)
 {
-    const u32 tid = threadIdx.x, lane = lane_id();
+    const u32 tid = bt_tid(), lane = tid & (WAVE - 1);
     const u32 w = __builtin_amdgcn_readfirstlane(tid / WAVE);
     const bool packed = n < 65536u;
     u64 pref[2] = {0ull, 0ull};
@@ -212,33 +242,47 @@ __device__ void bt_select(SRC src, u32 n, int top, const u64 rank_in[2], const b
 }
 
 // Write the columns of the pairs <= tau among src(0 .. n-1), in source order,
-// to out[0 ..) (at most `limit`).  Thread t takes runs of BT_IPT consecutive
-// pairs of each step, so source order is thread order within a step.
+// to out[0 ..) (at most `limit`).  A step of BT_STEP pairs gives wave w the
+// pairs [s0 + 1024 w, s0 + 1024 w + 1024) as 16 columns of 64 lanes (LDS
+// reads without bank conflicts); the waves' counts are exchanged once per
+// step, then every wave writes its pairs in order.
 template <class SRC>
 __device__ void bt_emit(SRC src, u32 n, u64 tau, u32 *out, u32 limit, BtShared &sh)
 {
-    const u32 tid = threadIdx.x;
+    const u32 tid = bt_tid(), lane = tid & (WAVE - 1);
+    const u32 w = __builtin_amdgcn_readfirstlane(tid / WAVE);
     u32 cur = 0;
     for (u32 s0 = 0; s0 < n; s0 += BT_STEP) {
-        u64 v[BT_IPT];
-        u32 c = 0;
+        const u32 b0 = s0 + w * (BT_STEP / BT_WAVES);
+        u32 bits = 0, c = 0;
 #pragma unroll
-        for (int j = 0; j < BT_IPT; ++j) {
-            const u32 i = s0 + tid * BT_IPT + (u32)j;
-            v[j] = i < n ? src(i) : ~0ull;
-            c += (i < n && v[j] <= tau) ? 1u : 0u;
+        for (int j = 0; j < 16; ++j) {
+            const u32 i = b0 + (u32)j * WAVE + lane;
+            const bool t = i < n && src(i) <= tau;
+            bits |= (u32)t << j;
+            c += (u32)__popcll(ballot(t));
         }
-        u32 tot;
-        u32 pos = cur + block_excl_scan<BT_THREADS>(c, sh.scan, &tot);
+        if (lane == 0) sh.scan[w] = c;
+        __syncthreads();
+        u32 pos = cur, tot = 0;
 #pragma unroll
-        for (int j = 0; j < BT_IPT; ++j) {
-            const u32 i = s0 + tid * BT_IPT + (u32)j;
-            if (i < n && v[j] <= tau) {
-                if (pos < limit) out[pos] = (u32)v[j];
-                ++pos;
+        for (int v = 0; v < BT_WAVES; ++v) {
+            const u32 sv = __builtin_amdgcn_readfirstlane(sh.scan[v]);
+            pos += (u32)v < w ? sv : 0u;
+            tot += sv;
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const bool t = (bits >> j) & 1u;
+            const u64 m = ballot(t);
+            if (t) {
+                const u32 q = pos + mbcnt(m);
+                if (q < limit) out[q] = (u32)src(b0 + (u32)j * WAVE + lane);
             }
+            pos += (u32)__popcll(m);
         }
         cur += tot;
+        __syncthreads();            // sh.scan is rewritten by the next step
     }
 }
 
@@ -276,10 +320,335 @@ __device__ __forceinline__ int bt_sample(u32 t, u64 len, u32 s_target, u64 seed,
     return cnt;
 }
 
+// Float value whose key order word is o (o not the NaN image).
 template <bool LARGEST>
-__device__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
+__device__ __forceinline__ float ord_value(u32 o)
 {
-    const u32 tid = threadIdx.x;
+    const u32 v = LARGEST ? ~o : o;
+    return __uint_as_float((v & 0x80000000u) ? (v & 0x7FFFFFFFu) : ~v);
+}
+
+template <bool LARGEST>
+__device__ __forceinline__ bool ord_is_nan(u32 o) { return (LARGEST ? ~o : o) == 0xFFFFFFFFu; }
+
+// 16 keys per lane of one sweep step: columns s0 + (16 j + 4 w) ... interleaved
+// so that wave w holds columns s0 + (j * BT_WAVES + w) * 64 + lane.
+template <bool GUARD>
+__device__ __forceinline__ void bt_load_step(const u32 *__restrict__ row, u32 s0, u32 len, u32 w,
+                                             u32 lane, u32 (&x)[16])
+{
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const u32 col = s0 + ((u32)j * BT_WAVES + w) * WAVE + lane;
+        x[j] = row[GUARD ? (col < len ? col : len - 1) : col];
+    }
+}
+
+// Fast sweep, one step of one wave: the keys at or below the upper pivot R
+// (compared as floats: for a pivot value that is not NaN, the float order and
+// the key order agree, -0 and +0 included) are appended with their column to
+// the wave's own LDS region; `na` counts those below the lower pivot L.  The
+// regions of the waves are independent, so the sweep needs no barrier.
+template <bool LARGEST, bool TAIL>
+__device__ __forceinline__ void bt_fast_step(const u32 (&x)[16], u32 s0, u32 len, u32 w, u32 lane,
+                                             float fL, float fR, u64 *reg, u32 &cnt, u32 &na)
+{
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const u32 col = s0 + ((u32)j * BT_WAVES + w) * WAVE + lane;
+        const float f = __uint_as_float(x[j]);
+        // largest: NaN keys come first, so "not below R" and "not at or below L"
+        bool ab = LARGEST ? !(f < fR) : (f <= fR);
+        bool ia = LARGEST ? !(f <= fL) : (f < fL);
+        if (TAIL) {
+            const bool ok = col < len;
+            ab = ab && ok;
+            ia = ia && ok;
+        }
+        const u64 m = ballot(ab);
+        // past the region's end every write lands on its last slot: the
+        // count then exceeds BT_REG and the caller discards the region
+        u32 q = cnt + mbcnt(m);
+        q = q < BT_REG - 1 ? q : BT_REG - 1;
+        if (ab) {
+            u32 *e = (u32 *)(reg + q);
+            e[0] = col;
+            e[1] = x[j];
+        }
+        cnt += (u32)__popcll(m);
+        na += (u32)__popcll(ballot(ia));
+        asm volatile("" : "+s"(cnt), "+s"(na));     // keep the sums current
+    }
+}
+
+// The whole fast sweep of one wave over the row, loads one step ahead.
+template <bool LARGEST>
+__device__ __forceinline__ void bt_fast_sweep(const u32 *__restrict__ row, u32 len, float fL, float fR, bool hl,
+                              u64 *reg, u32 &cnt_out, u32 &na_out)
+{
+    const u32 tid = bt_tid();
+    const u32 w = __builtin_amdgcn_readfirstlane(tid / WAVE), lane = tid & (WAVE - 1);
+    u32 cnt = 0, na = 0;
+    u32 x[16], y[16];
+    auto load = [&](u32 (&v)[16], u32 s0) {
+        if (s0 + BT_STEP <= len) bt_load_step<false>(row, s0, len, w, lane, v);
+        else bt_load_step<true>(row, s0, len, w, lane, v);
+    };
+    auto step = [&](const u32 (&v)[16], u32 s0) {
+        if (s0 + BT_STEP <= len) bt_fast_step<LARGEST, false>(v, s0, len, w, lane, fL, fR, reg, cnt, na);
+        else bt_fast_step<LARGEST, true>(v, s0, len, w, lane, fL, fR, reg, cnt, na);
+    };
+    u32 s0 = 0;
+    load(x, 0);
+    for (;;) {
+        // the next step's loads go out before this step is classified (past
+        // the end: the last step again, whose addresses are valid)
+        const u32 s1 = s0 + BT_STEP < len ? s0 + BT_STEP : s0;
+        load(y, s1);
+        step(x, s0);
+        if (s1 == s0) break;
+        s0 = s1;
+        const u32 s2 = s0 + BT_STEP < len ? s0 + BT_STEP : s0;
+        load(x, s2);
+        step(y, s0);
+        if (s2 == s0) break;
+        s0 = s2;
+    }
+    cnt_out = cnt;
+    na_out = hl ? na : 0u;          // no lower pivot: nothing lies below it
+}
+
+// Rank `rank` (0-based) among the fast sweep's candidates, the pairs
+// sh.buf[v BT_REG + (0 .. cnt[v])) of the waves v, which are a prefix of the
+// row's order; the band [ordL, ordR] of key order words holds the target
+// unless the pivots missed.  One histogram pass: bin 0 counts the order words
+// below ordL (by ballots), bins 1 .. by (o - ordL) >> shift, the last bin
+// anything above ordR.  A target bin of at most 64 pairs is ranked by one
+// wave; otherwise the generic radix select over the slots decides (`ssrc`:
+// empty slots read as ~0, above every candidate).
+template <class SRC>
+__device__ __forceinline__ u64 bt_band_tau(SRC ssrc, const u32 (&cnt)[BT_WAVES], u32 ordL, u32 ordR,
+                                           u32 rank, BtShared &sh)
+{
+    const u32 tid = bt_tid(), lane = tid & (WAVE - 1);
+    const u32 w = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    const u32 span = ordR - ordL;
+    u32 shift = 0;
+    while ((span >> shift) > BT_BINS - 3) ++shift;
+    auto bin = [&](u64 c) -> u32 {
+        const u32 o = (u32)(c >> 32);
+        if (o < ordL) return 0u;
+        const u32 b = 1u + ((o - ordL) >> shift);
+        return b < BT_BINS - 1 ? b : BT_BINS - 1;
+    };
+    for (u32 i = tid; i < BT_BINS; i += BT_THREADS) sh.hist[i] = 0u;
+    if (tid == 0) sh.ccount[0] = 0u;
+    __syncthreads();
+    u32 below = 0;
+#pragma unroll
+    for (int v = 0; v < BT_WAVES; ++v) {
+        for (u32 i = tid; i < cnt[v]; i += BT_THREADS) {
+            const u64 x = sh.buf[(u32)v * BT_REG + i];
+            const bool lo = (u32)(x >> 32) < ordL;
+            below += (u32)__popcll(ballot(lo));
+            if (!lo) atomicAdd(&sh.hist[bin(x)], 1u);
+        }
+    }
+    if (lane == 0 && below) atomicAdd(&sh.hist[0], below);
+    __syncthreads();
+    u32 c[BT_BPT], csum = 0;
+#pragma unroll
+    for (int q = 0; q < BT_BPT; ++q) {
+        c[q] = sh.hist[tid * BT_BPT + q];
+        sh.hist[tid * BT_BPT + q] = 0u;      // every bin is left at zero
+        csum += c[q];
+    }
+    u32 tot;
+    u32 before = block_excl_scan<BT_THREADS>(csum, sh.scan, &tot);
+#pragma unroll
+    for (int q = 0; q < BT_BPT; ++q) {
+        if (before <= rank && rank < before + c[q]) {
+            sh.sel_bin[0] = tid * BT_BPT + q;
+            sh.sel_before[0] = before;
+            sh.sel_count[0] = c[q];
+        }
+        before += c[q];
+    }
+    __syncthreads();
+    const u32 b = __builtin_amdgcn_readfirstlane(sh.sel_bin[0]);
+    const u32 nb = __builtin_amdgcn_readfirstlane(sh.sel_count[0]);
+    const u32 rr = rank - __builtin_amdgcn_readfirstlane(sh.sel_before[0]);
+    if (nb > (u32)WAVE) {
+        __syncthreads();
+        const u64 rk[2] = {(u64)rank, 0ull};
+        const bool one[2] = {true, false};
+        u64 t2[2];
+        bt_select(ssrc, BT_CAP, 64, rk, one, t2, sh);
+        return t2[0];
+    }
+#pragma unroll
+    for (int v = 0; v < BT_WAVES; ++v) {
+        for (u32 i = tid; i < cnt[v]; i += BT_THREADS) {
+            const u64 x = sh.buf[(u32)v * BT_REG + i];
+            if (bin(x) == b) sh.cand[0][atomicAdd(&sh.ccount[0], 1u)] = x;
+        }
+    }
+    __syncthreads();
+    if (w == 0) {
+        const u64 mine = lane < nb ? sh.cand[0][lane] : ~0ull;
+        const u32 mlo = (u32)mine, mhi = (u32)(mine >> 32);
+        u32 lt = 0;
+        for (u32 i = 0; i < nb; ++i) {
+            const u64 o = ((u64)(u32)__builtin_amdgcn_readlane((int)mhi, (int)i) << 32) |
+                          (u32)__builtin_amdgcn_readlane((int)mlo, (int)i);
+            lt += o < mine ? 1u : 0u;
+        }
+        if (lane < nb && lt == rr) sh.found[0] = mine;
+    }
+    __syncthreads();
+    return sh.found[0];
+}
+
+// Pair of rank `rank` (0-based) among the pairs (o[j], j BT_THREADS + tid)
+// held in registers (valid while the column is below n): radix select over
+// windows of BT_BITS bits of the 64-bit pair from the top, keeping the bucket
+// that holds the rank, until it has at most 64 pairs, which one wave ranks.
+// Every histogram bin is zero on entry and on return.
+template <int M>
+__device__ __forceinline__ u64 bt_reg_select(const u32 (&o)[M], u32 n, u32 rank, BtShared &sh)
+{
+    const u32 tid = bt_tid(), lane = tid & (WAVE - 1);
+    const u32 w = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    u32 ph = 0, pl = 0;                 // prefix: the bits at and above lowb are fixed
+    int lowb = 64;
+    u32 rk = rank;
+    auto match = [&](u32 oj, u32 col) -> bool {
+        if (lowb >= 64) return true;
+        if (lowb >= 32) return (oj >> (lowb - 32)) == (ph >> (lowb - 32));
+        return oj == ph && (col >> lowb) == (pl >> lowb);
+    };
+    u32 cnt = n;
+    while (cnt > (u32)WAVE && lowb > 0) {
+        const int sh_ = lowb > BT_BITS ? lowb - BT_BITS : 0;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const u32 col = (u32)j * BT_THREADS + tid;
+            if (col < n && match(o[j], col))
+                atomicAdd(&sh.hist[(u32)(pack(o[j], col) >> sh_) & (BT_BINS - 1)], 1u);
+        }
+        __syncthreads();
+        u32 c[BT_BPT], csum = 0;
+#pragma unroll
+        for (int q = 0; q < BT_BPT; ++q) {
+            c[q] = sh.hist[tid * BT_BPT + q];
+            sh.hist[tid * BT_BPT + q] = 0u;
+            csum += c[q];
+        }
+        u32 tot;
+        u32 before = block_excl_scan<BT_THREADS>(csum, sh.scan, &tot);
+#pragma unroll
+        for (int q = 0; q < BT_BPT; ++q) {
+            if (before <= rk && rk < before + c[q]) {
+                sh.sel_bin[0] = tid * BT_BPT + q;
+                sh.sel_before[0] = before;
+                sh.sel_count[0] = c[q];
+            }
+            before += c[q];
+        }
+        __syncthreads();
+        const u64 bsel = (u64)__builtin_amdgcn_readfirstlane(sh.sel_bin[0]) << sh_;
+        cnt = __builtin_amdgcn_readfirstlane(sh.sel_count[0]);
+        rk -= __builtin_amdgcn_readfirstlane(sh.sel_before[0]);
+        ph |= (u32)(bsel >> 32);
+        pl |= (u32)bsel;
+        lowb = sh_;
+    }
+    if (lowb == 0) return ((u64)ph << 32) | pl;     // every bit fixed: that pair
+    if (tid == 0) sh.ccount[0] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const u32 col = (u32)j * BT_THREADS + tid;
+        if (col < n && match(o[j], col)) sh.cand[0][atomicAdd(&sh.ccount[0], 1u)] = pack(o[j], col);
+    }
+    __syncthreads();
+    if (w == 0) {
+        const u64 mine = lane < cnt ? sh.cand[0][lane] : ~0ull;
+        const u32 mlo = (u32)mine, mhi = (u32)(mine >> 32);
+        u32 lt = 0;
+        for (u32 i = 0; i < cnt; ++i) {
+            const u64 x = ((u64)(u32)__builtin_amdgcn_readlane((int)mhi, (int)i) << 32) |
+                          (u32)__builtin_amdgcn_readlane((int)mlo, (int)i);
+            lt += x < mine ? 1u : 0u;
+        }
+        if (lane < cnt && lt == rk) sh.found[0] = mine;
+    }
+    __syncthreads();
+    return sh.found[0];
+}
+
+// Write the columns of the register pairs <= tau in column order to out[0 ..)
+// (at most `limit`): per column block j the waves' counts go to LDS, one
+// barrier, then each wave writes at its place.
+template <int M>
+__device__ __forceinline__ void bt_reg_emit(const u32 (&o)[M], u32 n, u64 tau, u32 *out, u32 limit,
+                                            BtShared &sh)
+{
+    const u32 tid = bt_tid(), lane = tid & (WAVE - 1);
+    const u32 w = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    u32 *cnts = sh.ecnt;                // [M][BT_WAVES]
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const u32 col = (u32)j * BT_THREADS + tid;
+        const u32 c = (u32)__popcll(ballot(col < n && pack(o[j], col) <= tau));
+        if (lane == 0) cnts[j * BT_WAVES + w] = c;
+    }
+    __syncthreads();
+    u32 pos = 0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const u32 col = (u32)j * BT_THREADS + tid;
+        const bool t = col < n && pack(o[j], col) <= tau;
+        const u64 m = ballot(t);
+        u32 mine = pos, all = 0;
+#pragma unroll
+        for (int v = 0; v < BT_WAVES; ++v) {
+            const u32 cv = __builtin_amdgcn_readfirstlane(cnts[j * BT_WAVES + v]);
+            mine += (u32)v < w ? cv : 0u;
+            all += cv;
+        }
+        if (t) {
+            const u32 q = mine + mbcnt(m);
+            if (q < limit) out[q] = col;
+        }
+        pos += all;
+    }
+    __syncthreads();                    // cnts is reused
+}
+
+// A row of at most M BT_THREADS keys, held in registers as key order words.
+template <bool LARGEST, int M>
+__device__ __forceinline__ u64 bt_reg_row(const u32 *__restrict__ row, u32 len, u32 k, u32 *out,
+                                          BtShared &sh)
+{
+    const u32 tid = bt_tid();
+    u32 o[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const u32 col = (u32)j * BT_THREADS + tid;
+        o[j] = col < len ? row[col] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < M; ++j) o[j] = key_ord<true, LARGEST>(o[j]);
+    const u64 tau = bt_reg_select<M>(o, len, k - 1, sh);
+    bt_reg_emit<M>(o, len, tau, out, k, sh);
+    return tau;
+}
+
+template <bool LARGEST>
+__device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
+{
+    const u32 tid = bt_tid();
     const u64 off = a.row_off[r];
     const u64 len64 = a.row_off[r + 1] - off;
     const u32 k = a.k[r];
@@ -292,32 +661,33 @@ __device__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
     u32 *__restrict__ out = a.out_idx + a.out_off[r];
     auto gsrc = [&](u32 i) -> u64 { return pack(key_ord<true, LARGEST>(row[i]), i); };
     auto lsrc = [&](u32 i) -> u64 { return sh.buf[i]; };
+    // fast sweep regions as slots: wave v's candidates at v * BT_REG + [0, count)
+    auto ssrc = [&](u32 i) -> u64 {
+        return (i & (BT_REG - 1)) < sh.wt[0][i / BT_REG] ? sh.buf[i] : ~0ull;
+    };
 
     u32 na = 0, nb = len;
-    bool in_lds = false;
+    bool in_lds = false, fast_done = false;
+    u64 fast_tau = 0;
     int band_top = 64;                  // pairs in LDS agree at and above this bit
-    if (len <= BT_CAP) {
-        u32 x[BT_CAP / BT_THREADS];                // all loads first, one wait
-#pragma unroll
-        for (int j = 0; j < (int)(BT_CAP / BT_THREADS); ++j) {
-            const u32 i = (u32)j * BT_THREADS + tid;
-            x[j] = i < len ? row[i] : 0u;
-        }
-#pragma unroll
-        for (int j = 0; j < (int)(BT_CAP / BT_THREADS); ++j) {
-            const u32 i = (u32)j * BT_THREADS + tid;
-            if (i < len) sh.buf[i] = pack(key_ord<true, LARGEST>(x[j]), i);
-        }
-        __syncthreads();
-        in_lds = true;
+    bool reg_done = false;
+    u64 reg_tau = 0;
+    if (len <= BT_REG_KEYS / 4) {
+        reg_tau = bt_reg_row<LARGEST, BT_REG_KEYS / 4 / BT_THREADS>(row, len, k, out, sh);
+        reg_done = true;
+    } else if (len <= BT_REG_KEYS) {
+        reg_tau = bt_reg_row<LARGEST, BT_REG_KEYS / BT_THREADS>(row, len, k, out, sh);
+        reg_done = true;
     } else {
         u32 c_num = a.c_num;
-        for (u32 att = 0; att < a.attempts && !in_lds; ++att) {
+        bool fast_ok = a.fast != 0u;    // until a fast sweep overflows its region
+        for (u32 att = 0; att < a.attempts && !in_lds && !fast_done; ++att) {
             // sample -> LDS, compacted
             u32 pos[BT_SEG];
             const int cnt = bt_sample(tid, len, a.s_target, a.seed, att, r, pos);
             u32 s;
             const u32 at = block_excl_scan<BT_THREADS>((u32)cnt, sh.scan, &s);
+            s = __builtin_amdgcn_readfirstlane(s);
 #pragma unroll
             for (int j = 0; j < BT_SEG; ++j)
                 if (j < cnt) sh.buf[at + (u32)j] = gsrc(pos[j]);
@@ -331,15 +701,56 @@ __device__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
                 const bool ac[2] = {hl, hr};
                 bt_select(lsrc, s, 64, rk, ac, piv, sh);
             }
-            const u64 L = hl ? piv[0] : 0ull;
-            const u64 R = hr ? piv[1] : ~0ull;
+            const u64 L = hl ? uniform64(piv[0]) : 0ull;
+            const u64 R = hr ? uniform64(piv[1]) : ~0ull;
+            const u32 oL = (u32)(L >> 32), oR = (u32)(R >> 32);
+            if (fast_ok && hr && !ord_is_nan<LARGEST>(oR) && !(hl && ord_is_nan<LARGEST>(oL)) &&
+                (u64)(hi + 1) * len * BT_FAST_DEN <= (u64)s * BT_FAST_NUM * BT_CAP) {
+                // fast sweep: candidates (<= R) into per-wave regions of sh.buf
+                const u32 wv = __builtin_amdgcn_readfirstlane(tid / WAVE), ln = tid & (WAVE - 1);
+                __syncthreads();
+                u32 cw, aw;
+                u64 *reg = sh.buf + wv * BT_REG;
+                bt_fast_sweep<LARGEST>(row, len, hl ? ord_value<LARGEST>(oL) : 0.0f,
+                                       ord_value<LARGEST>(oR), hl, reg, cw, aw);
+                // the wave's own region to (ord, column) pairs, in place
+                for (u32 i = ln; i < cw && i < BT_REG; i += WAVE) {
+                    const u64 e = reg[i];
+                    reg[i] = pack(key_ord<true, LARGEST>((u32)(e >> 32)), (u32)e);
+                }
+                if (ln == 0) {
+                    sh.wt[0][wv] = cw;
+                    sh.wt[1][wv] = aw;
+                }
+                __syncthreads();
+                u32 n_ab = 0, n_a = 0, cnt[BT_WAVES];
+                bool over = false;
+#pragma unroll
+                for (int v = 0; v < BT_WAVES; ++v) {
+                    cnt[v] = __builtin_amdgcn_readfirstlane(sh.wt[0][v]);
+                    over = over || cnt[v] > BT_REG;
+                    n_ab += cnt[v];
+                    n_a += __builtin_amdgcn_readfirstlane(sh.wt[1][v]);
+                }
+                if (!over) {
+                    if (n_a >= k || n_ab < k) {
+                        c_num *= 2;          // the pivots missed rank k: wider
+                        continue;
+                    }
+                    fast_tau = bt_band_tau(ssrc, cnt, hl ? oL : 0u, oR, k - 1, sh);
+                    fast_done = true;
+                    break;
+                }
+                fast_ok = false;             // region overflow: the general sweep, same pivots
+                __syncthreads();             // (it rewrites sh.wt, read above)
+            }
             // one sweep: below L -> output, [L, R] -> LDS band.  Wave w takes
             // keys [s0 + 1024 w, s0 + 1024 w + 1024) of a step as 16 columns of
             // 64 lanes (coalesced); lane bits keep its keys' parts; the waves'
             // counts are exchanged once per step.
             u32 ca = 0, cb = 0;
             {
-                const u32 wv = __builtin_amdgcn_readfirstlane(tid / WAVE), ln = lane_id();
+                const u32 wv = __builtin_amdgcn_readfirstlane(tid / WAVE), ln = tid & (WAVE - 1);
                 for (u32 s0 = 0, st = 0; s0 < len; s0 += BT_STEP, ++st) {
                     const u32 base = s0 + wv * (BT_STEP / BT_WAVES);
                     u32 o[16];
@@ -412,7 +823,12 @@ __device__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
     u64 tau;
     const bool one[2] = {true, false};
     u64 t2[2];
-    if (in_lds) {
+    if (reg_done) {
+        tau = reg_tau;
+    } else if (fast_done) {
+        tau = fast_tau;
+        bt_emit(ssrc, BT_CAP, tau, out, k, sh);
+    } else if (in_lds) {
         const u64 rk[2] = {(u64)(k - na - 1), 0ull};
         bt_select(lsrc, nb, band_top, rk, one, t2, sh);
         tau = t2[0];
@@ -426,7 +842,7 @@ __device__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
     }
     if (tid == 0) {
         a.kth_idx[r] = (u32)tau;
-        a.kth_key[r] = row[(u32)tau];
+        a.kth_key[r] = (u32)tau < len ? row[(u32)tau] : 0u;
     }
     __syncthreads();
 }
@@ -435,12 +851,14 @@ template <bool LARGEST>
 __global__ __launch_bounds__(BT_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_batched(BtArgs a)
 {
     __shared__ BtShared sh;
+    for (u32 i = threadIdx.x; i < BT_BINS; i += BT_THREADS) sh.hist[i] = 0u;
+    __syncthreads();
     // rows in longest-first order from a queue: one row per grab for the first
     // BT_Q1 positions (the long rows), then BT_QCHUNK rows per grab
     for (;;) {
         if (threadIdx.x == 0) sh.next = atomicAdd(a.queue, 1u);
         __syncthreads();
-        const u32 g = sh.next;
+        const u32 g = __builtin_amdgcn_readfirstlane(sh.next);
         __syncthreads();
         const u32 p0 = g < BT_Q1 ? g : BT_Q1 + (g - BT_Q1) * BT_QCHUNK;
         if (p0 >= a.rows) break;
@@ -587,6 +1005,7 @@ extern "C" int topk_select_batched_f32(topk_ctx *c, const float *keys, const uin
     a.s_target = (u32)c->bt_s_target;
     a.c_num = (u32)c->bt_c_num;
     a.attempts = (u32)c->bt_attempts;
+    a.fast = (u32)c->bt_fast;
     if (hipSetDevice(c->device) != hipSuccess) return TOPK_E_HIP;
     const int grid = (int)(c->num_cu * c->bt_wg_per_cu);   // 4 fit on a CU (LDS, registers)
     if (!(flags & TOPK_GRAPH))
@@ -597,7 +1016,8 @@ extern "C" int topk_select_batched_f32(topk_ctx *c, const float *keys, const uin
         (uint64_t)(uintptr_t)keys, (uint64_t)(uintptr_t)row_off, rows, (uint64_t)(uintptr_t)k,
         (uint64_t)(uintptr_t)out_off, a.flags, (uint64_t)(uintptr_t)out_idx,
         (uint64_t)(uintptr_t)kth_key, (uint64_t)(uintptr_t)kth_idx, (uint64_t)(uintptr_t)status,
-        (uint64_t)(uintptr_t)workspace, a.seed, a.s_target, a.c_num, a.attempts, (uint64_t)grid};
+        (uint64_t)(uintptr_t)workspace, a.seed, a.s_target, a.c_num, a.attempts, a.fast,
+        (uint64_t)grid};
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
         if (!c->capture_stream &&

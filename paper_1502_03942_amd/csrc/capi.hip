@@ -194,6 +194,7 @@ int topk_create(topk_ctx **out, int hip_device, uint64_t seed)
     c->bt_c_num = 24;
     c->bt_wg_per_cu = 4;
     c->bt_attempts = 4;
+    c->bt_fast = 1;
     c->num_cu = ncu;
     *out = c;
     return TOPK_OK;
@@ -224,6 +225,7 @@ int topk_set_param(topk_ctx *c, const char *name, int64_t v)
         {"bt_c_num", &c->bt_c_num, 4, 4096},
         {"bt_wg_per_cu", &c->bt_wg_per_cu, 1, 8},
         {"bt_attempts", &c->bt_attempts, 1, 16},
+        {"bt_fast", &c->bt_fast, 0, 1},
     };
     if (strcmp(name, "seed") == 0) { c->seed = (uint64_t)v; return TOPK_OK; }
     for (auto &e : tab) {
@@ -246,6 +248,7 @@ int topk_get_param(const topk_ctx *c, const char *name, int64_t *v)
         {"tail_max", c->tail_max}, {"timing", c->timing},
         {"bt_s_target", c->bt_s_target}, {"bt_c_num", c->bt_c_num},
         {"bt_wg_per_cu", c->bt_wg_per_cu}, {"bt_attempts", c->bt_attempts},
+        {"bt_fast", c->bt_fast},
     };
     for (auto &e : tab) {
         if (strcmp(name, e.n) == 0) { *v = e.val; return TOPK_OK; }

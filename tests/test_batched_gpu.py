@@ -142,3 +142,36 @@ def test_batched_fullsize(dev):
     sample = sorted(set(longest + list(range(0, 65536, 997))))
     check_rows(keys, off, kk, res, False, rows=sample, full=True)
     check_rows(keys, off, kk, res, False, full=False)
+
+
+@pytest.mark.parametrize("fast", [0, 1])
+@pytest.mark.parametrize("largest", [False, True])
+def test_batched_fast_and_general_agree(dev, fast, largest):
+    # the same rows through the fast sweep and through the general sweep
+    rng = np.random.default_rng(40)
+    lens = [4097, 6000, 13000, 33000, 100000, 262144, 9000, 20000]
+    ks = [1, 2048, 700, 2048, 1, 1500, 9000, 20000]
+    keys, off, kk = ragged(lens, ks, lambda n: synth.specials_f32(n, 41))
+    ctx = tk.Context(0, seed=9).set_param("bt_fast", fast)
+    res = ctx.select_batched(*to_dev(keys, off, kk, dev), largest=largest)
+    check_rows(keys, off, kk, res, largest)
+
+
+@pytest.mark.parametrize("largest", [False, True])
+def test_batched_structured_long_rows(dev, largest):
+    # sorted and reverse-sorted rows put every candidate in a few columns;
+    # constant and two-valued rows tie at the pivots: region overflows and
+    # band overflows fall back to the general sweep or the exact select
+    n = 30000
+    up = np.arange(n, dtype=np.float32)
+    rows = [up, up[::-1].copy(), np.full(n, 3.0, np.float32),
+            np.where(np.arange(n) % 7 == 0, 1.0, 2.0).astype(np.float32),
+            np.concatenate([np.full(n // 2, -1.0, np.float32), up[: n - n // 2]])]
+    ks = [2048, 1000, 1500, 2048, 700]
+    off = np.zeros(len(rows) + 1, np.uint64)
+    off[1:] = np.cumsum([len(r) for r in rows])
+    keys = np.concatenate(rows)
+    kk = np.array(ks, np.uint32)
+    ctx = tk.Context(0, seed=11)
+    res = ctx.select_batched(*to_dev(keys, off, kk, dev), largest=largest)
+    check_rows(keys, off, kk, res, largest)
