@@ -181,9 +181,12 @@ int topk_kernel_times(topk_ctx *ctx, float *ms, int32_t *kind, uint32_t max, uin
  * first; each row by the sampling method with the workgroup as the machine
  * (batched.hip).  Context parameters tune it:
  *   "bt_s_target"  1024  expected sample size of a long row; 64..2048
- *   "bt_c_num"       24  pivot spread (as c_num above); 4..4096
+ *   "bt_c_num"       12  pivot spread (as c_num above); 4..4096
  *   "bt_wg_per_cu"    4  resident workgroups per CU of the persistent grid; 1..8
  *   "bt_attempts"     4  sampling attempts before the exact fallback; 1..16
+ *   "bt_s_target@C", "bt_c_num@C"  the same for the rows of length class C
+ *                        only (lengths [2^(C-1), 2^C), 0 <= C < 34); -1
+ *                        (default) falls back to the value above
  *   "bt_fast"         1  1: a row whose expected candidates (keys up to the
  *                        upper pivot) fit 0.7 of the workgroup's 4096 LDS
  *                        slots is swept once into per-wave LDS regions; 0:
@@ -201,6 +204,33 @@ int topk_select_batched_f32(topk_ctx *ctx, const float *keys, const uint64_t *ro
                             uint32_t flags, uint32_t *out_idx, float *kth_key,
                             uint32_t *kth_idx, uint32_t *status, void *workspace,
                             size_t ws_bytes, hipStream_t stream);
+
+/* topk_tune_batched_f32: the autotuner of the batched form.  Same arguments
+ * as topk_select_batched_f32 (TOPK_GRAPH ignored; the outputs are
+ * overwritten with valid results).  For every length class of the batch whose
+ * rows take the sampling path (longer than 8192 keys), the batch restricted to
+ * that class is timed (median of `reps` calls, HIP events on `stream`) under
+ * each pair bt_s_target in {256, 512, 1024, 2048} x bt_c_num in
+ * {8, 12, 16, 24}; the fastest pair becomes the class's "bt_s_target@C" /
+ * "bt_c_num@C".  Then "bt_wg_per_cu" in {2, 3, 4} is timed over the whole
+ * batch and the fastest kept.  Blocks the host until the stream is idle.
+ * Returns TOPK_OK, the errors of topk_select_batched_f32, or TOPK_E_INVALID
+ * for reps outside 1..100. */
+int topk_tune_batched_f32(topk_ctx *ctx, const float *keys, const uint64_t *row_off,
+                          uint32_t rows, const uint32_t *k, const uint64_t *out_off,
+                          uint32_t flags, uint32_t *out_idx, float *kth_key,
+                          uint32_t *kth_idx, uint32_t *status, void *workspace,
+                          size_t ws_bytes, uint32_t reps, hipStream_t stream);
+
+/* Tuning files (host paths): a flat JSON object of "name": integer pairs,
+ * the parameter names of topk_set_param ("seed" and "timing" excluded).
+ * topk_save_tuning writes every tuning parameter and every length-class
+ * override of ctx.  topk_load_tuning applies a file all or nothing (an unknown
+ * name, a value out of range or a syntax error leaves ctx unchanged and
+ * returns TOPK_E_INVALID); path NULL restores the built-in defaults.  Both
+ * return TOPK_OK or TOPK_E_INVALID (also for a file that cannot be opened). */
+int topk_save_tuning(const topk_ctx *ctx, const char *path);
+int topk_load_tuning(topk_ctx *ctx, const char *path);
 
 /* ---- Row-wise top-k (a differentiable layer's forward and backward) ----
  *

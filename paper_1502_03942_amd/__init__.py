@@ -72,6 +72,9 @@ def lib():
     L.topk_batched_workspace_bytes.argtypes = [vp, u32, u32]
     L.topk_batched_workspace_bytes.restype = sz
     L.topk_select_batched_f32.argtypes = [vp, vp, vp, u32, vp, vp, u32, vp, vp, vp, vp, vp, sz, vp]
+    L.topk_tune_batched_f32.argtypes = [vp, vp, vp, u32, vp, vp, u32, vp, vp, vp, vp, vp, sz, u32, vp]
+    L.topk_save_tuning.argtypes = [vp, ctypes.c_char_p]
+    L.topk_load_tuning.argtypes = [vp, ctypes.c_char_p]
     L.topk_rows_fwd_f32.argtypes = [vp, vp, u32, u32, u32, u32, vp, vp, vp]
     L.topk_scatter_bwd_f32.argtypes = [vp, vp, u32, u32, u32, vp, vp]
     L.topk_strerror.argtypes = [i32]
@@ -203,6 +206,26 @@ class Context:
             _ptr(out["idx"]), _ptr(out["kth_key"]), _ptr(out["kth_idx"]), _ptr(out["status"]),
             _ptr(ws), ws.numel(), _stream(keys.device)))
         return out
+
+    def tune_batched(self, keys, row_off, k, out_off=None, largest=False, reps=3, out=None):
+        """Autotune the batched form on this batch (topk_tune_batched_f32);
+        returns the output dict of the last timed call (valid results)."""
+        out = self.select_batched(keys, row_off, k, out_off=out_off, largest=largest, out=out)
+        R = row_off.numel() - 1
+        ws = out["workspace"]
+        _check(lib().topk_tune_batched_f32(
+            self._h, _ptr(keys), _ptr(row_off), R, _ptr(k), _ptr(out["out_off"]),
+            TOPK_LARGEST if largest else 0, _ptr(out["idx"]), _ptr(out["kth_key"]),
+            _ptr(out["kth_idx"]), _ptr(out["status"]), _ptr(ws), ws.numel(), int(reps),
+            _stream(keys.device)))
+        return out
+
+    def save_tuning(self, path):
+        _check(lib().topk_save_tuning(self._h, os.fsencode(path)))
+
+    def load_tuning(self, path=None):
+        _check(lib().topk_load_tuning(self._h, None if path is None else os.fsencode(path)))
+        return self
 
     def kernel_times(self, max_records=1 << 16):
         """Durations (ms) of the kernels recorded with param "timing" > 0 since

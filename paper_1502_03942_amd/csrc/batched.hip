@@ -35,6 +35,7 @@
 #include <hip/hip_runtime.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "common.hpp"
@@ -64,7 +65,7 @@ struct BtShared {
     u64 buf[BT_CAP];
     u32 hist[BT_BINS];          // two targets' counts packed (low / high 16 bits)
     u64 cand[2][WAVE];
-    u32 ecnt[BT_REG_KEYS / BT_THREADS * BT_WAVES];   // short row emit: counts per column block and wave
+    alignas(16) u32 ecnt[BT_REG_KEYS / BT_THREADS][BT_WAVES];   // short row emit: counts per column block, wave
     u64 rmin[2], rmax[2], found[2];
     u32 ccount[2], sel_bin[2], sel_before[2], sel_count[2];
     u32 scan[BT_WAVES];
@@ -81,7 +82,9 @@ struct BtArgs {
     u32 *out_idx, *kth_key, *kth_idx, *status;
     u32 *cls_cnt, *cls_fill, *order, *queue;
     u64 seed;
-    u32 s_target, c_num, attempts, fast;
+    u32 attempts, fast;
+    u32 cls_lo, cls_hi;                 // only rows of these length classes
+    u32 s_cls[BT_NCLS], c_cls[BT_NCLS]; // sample size and spread by length class
 };
 
 __device__ __forceinline__ u32 len_class(u64 len)
@@ -513,12 +516,14 @@ __device__ __forceinline__ u64 bt_band_tau(SRC ssrc, const u32 (&cnt)[BT_WAVES],
 // held in registers (valid while the column is below n): radix select over
 // windows of BT_BITS bits of the 64-bit pair from the top, keeping the bucket
 // that holds the rank, until it has at most 64 pairs, which one wave ranks.
+// Column blocks j at or past ceil(n / BT_THREADS) are skipped as a whole.
 // Every histogram bin is zero on entry and on return.
 template <int M>
 __device__ __forceinline__ u64 bt_reg_select(const u32 (&o)[M], u32 n, u32 rank, BtShared &sh)
 {
     const u32 tid = bt_tid(), lane = tid & (WAVE - 1);
     const u32 w = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    const u32 jn = (n + BT_THREADS - 1) / BT_THREADS;
     u32 ph = 0, pl = 0;                 // prefix: the bits at and above lowb are fixed
     int lowb = 64;
     u32 rk = rank;
@@ -532,9 +537,14 @@ __device__ __forceinline__ u64 bt_reg_select(const u32 (&o)[M], u32 n, u32 rank,
         const int sh_ = lowb > BT_BITS ? lowb - BT_BITS : 0;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-            const u32 col = (u32)j * BT_THREADS + tid;
-            if (col < n && match(o[j], col))
-                atomicAdd(&sh.hist[(u32)(pack(o[j], col) >> sh_) & (BT_BINS - 1)], 1u);
+            if ((u32)j < jn) {
+                const u32 col = (u32)j * BT_THREADS + tid;
+                if (col < n && match(o[j], col)) {
+                    const u32 d = sh_ >= 32 ? (o[j] >> (sh_ - 32)) & (BT_BINS - 1)
+                                            : (u32)(pack(o[j], col) >> sh_) & (BT_BINS - 1);
+                    atomicAdd(&sh.hist[d], 1u);
+                }
+            }
         }
         __syncthreads();
         u32 c[BT_BPT], csum = 0;
@@ -568,8 +578,10 @@ __device__ __forceinline__ u64 bt_reg_select(const u32 (&o)[M], u32 n, u32 rank,
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        const u32 col = (u32)j * BT_THREADS + tid;
-        if (col < n && match(o[j], col)) sh.cand[0][atomicAdd(&sh.ccount[0], 1u)] = pack(o[j], col);
+        if ((u32)j < jn) {
+            const u32 col = (u32)j * BT_THREADS + tid;
+            if (col < n && match(o[j], col)) sh.cand[0][atomicAdd(&sh.ccount[0], 1u)] = pack(o[j], col);
+        }
     }
     __syncthreads();
     if (w == 0) {
@@ -596,34 +608,38 @@ __device__ __forceinline__ void bt_reg_emit(const u32 (&o)[M], u32 n, u64 tau, u
 {
     const u32 tid = bt_tid(), lane = tid & (WAVE - 1);
     const u32 w = __builtin_amdgcn_readfirstlane(tid / WAVE);
-    u32 *cnts = sh.ecnt;                // [M][BT_WAVES]
+    const u32 jn = (n + BT_THREADS - 1) / BT_THREADS;
+    const u32 th = (u32)(tau >> 32), tl = (u32)tau;
+    static_assert(M <= 32, "one selection bit per column block");
+    u32 bits = 0;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        const u32 col = (u32)j * BT_THREADS + tid;
-        const u32 c = (u32)__popcll(ballot(col < n && pack(o[j], col) <= tau));
-        if (lane == 0) cnts[j * BT_WAVES + w] = c;
+        if ((u32)j < jn) {
+            const u32 col = (u32)j * BT_THREADS + tid;
+            const bool t = col < n && (o[j] < th || (o[j] == th && col <= tl));
+            bits |= (u32)t << j;
+            const u32 c = (u32)__popcll(ballot(t));
+            if (lane == 0) sh.ecnt[j][w] = c;
+        }
     }
     __syncthreads();
     u32 pos = 0;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        const u32 col = (u32)j * BT_THREADS + tid;
-        const bool t = col < n && pack(o[j], col) <= tau;
-        const u64 m = ballot(t);
-        u32 mine = pos, all = 0;
-#pragma unroll
-        for (int v = 0; v < BT_WAVES; ++v) {
-            const u32 cv = __builtin_amdgcn_readfirstlane(cnts[j * BT_WAVES + v]);
-            mine += (u32)v < w ? cv : 0u;
-            all += cv;
+        if ((u32)j < jn) {
+            const bool t = (bits >> j) & 1u;
+            const u64 m = ballot(t);
+            const uint4 c4 = *(const uint4 *)sh.ecnt[j];
+            const u32 all = c4.x + c4.y + c4.z + c4.w;
+            const u32 mine = pos + (w > 0 ? c4.x : 0u) + (w > 1 ? c4.y : 0u) + (w > 2 ? c4.z : 0u);
+            if (t) {
+                const u32 q = mine + mbcnt(m);
+                if (q < limit) out[q] = (u32)j * BT_THREADS + tid;
+            }
+            pos += all;
         }
-        if (t) {
-            const u32 q = mine + mbcnt(m);
-            if (q < limit) out[q] = col;
-        }
-        pos += all;
     }
-    __syncthreads();                    // cnts is reused
+    __syncthreads();                    // ecnt is reused
 }
 
 // A row of at most M BT_THREADS keys, held in registers as key order words.
@@ -632,11 +648,12 @@ __device__ __forceinline__ u64 bt_reg_row(const u32 *__restrict__ row, u32 len, 
                                           BtShared &sh)
 {
     const u32 tid = bt_tid();
+    const u32 jn = (len + BT_THREADS - 1) / BT_THREADS;
     u32 o[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
         const u32 col = (u32)j * BT_THREADS + tid;
-        o[j] = col < len ? row[col] : 0u;
+        o[j] = (u32)j < jn && col < len ? row[col] : 0u;
     }
 #pragma unroll
     for (int j = 0; j < M; ++j) o[j] = key_ord<true, LARGEST>(o[j]);
@@ -652,6 +669,8 @@ __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
     const u64 off = a.row_off[r];
     const u64 len64 = a.row_off[r + 1] - off;
     const u32 k = a.k[r];
+    const u32 cls = len_class(len64);
+    if (cls < a.cls_lo || cls > a.cls_hi) return;
     if (k == 0 || (u64)k > len64 || len64 > 0xFFFFFFFFull) {
         if (tid == 0) atomicOr(a.status, (u32)TOPK_STATUS_BAD_ROW);
         return;
@@ -672,19 +691,23 @@ __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
     int band_top = 64;                  // pairs in LDS agree at and above this bit
     bool reg_done = false;
     u64 reg_tau = 0;
-    if (len <= BT_REG_KEYS / 4) {
-        reg_tau = bt_reg_row<LARGEST, BT_REG_KEYS / 4 / BT_THREADS>(row, len, k, out, sh);
+    if (len <= BT_REG_KEYS / 8) {
+        reg_tau = bt_reg_row<LARGEST, BT_REG_KEYS / 8 / BT_THREADS>(row, len, k, out, sh);
+        reg_done = true;
+    } else if (len <= BT_REG_KEYS / 2) {
+        reg_tau = bt_reg_row<LARGEST, BT_REG_KEYS / 2 / BT_THREADS>(row, len, k, out, sh);
         reg_done = true;
     } else if (len <= BT_REG_KEYS) {
         reg_tau = bt_reg_row<LARGEST, BT_REG_KEYS / BT_THREADS>(row, len, k, out, sh);
         reg_done = true;
     } else {
-        u32 c_num = a.c_num;
+        u32 c_num = a.c_cls[cls];
+        const u32 s_target = a.s_cls[cls];
         bool fast_ok = a.fast != 0u;    // until a fast sweep overflows its region
         for (u32 att = 0; att < a.attempts && !in_lds && !fast_done; ++att) {
             // sample -> LDS, compacted
             u32 pos[BT_SEG];
-            const int cnt = bt_sample(tid, len, a.s_target, a.seed, att, r, pos);
+            const int cnt = bt_sample(tid, len, s_target, a.seed, att, r, pos);
             u32 s;
             const u32 at = block_excl_scan<BT_THREADS>((u32)cnt, sh.scan, &s);
             s = __builtin_amdgcn_readfirstlane(s);
@@ -969,11 +992,13 @@ extern "C" size_t topk_batched_workspace_bytes(const topk_ctx *ctx, uint32_t row
     return bt_layout(rows).total;
 }
 
-extern "C" int topk_select_batched_f32(topk_ctx *c, const float *keys, const uint64_t *row_off,
-                                       uint32_t rows, const uint32_t *k, const uint64_t *out_off,
-                                       uint32_t flags, uint32_t *out_idx, float *kth_key,
-                                       uint32_t *kth_idx, uint32_t *status, void *workspace,
-                                       size_t ws_bytes, hipStream_t stream)
+namespace {
+
+// Kernel arguments of one batched call (after the argument checks).
+int bt_args(const topk_ctx *c, const float *keys, const uint64_t *row_off, uint32_t rows,
+            const uint32_t *k, const uint64_t *out_off, uint32_t flags, uint32_t *out_idx,
+            float *kth_key, uint32_t *kth_idx, uint32_t *status, void *workspace,
+            size_t ws_bytes, BtArgs &a)
 {
     if (!c || !keys || !row_off || !k || !out_off || !out_idx || !kth_key || !kth_idx ||
         !status || !workspace)
@@ -986,7 +1011,7 @@ extern "C" int topk_select_batched_f32(topk_ctx *c, const float *keys, const uin
     const BtLayout L = bt_layout(rows);
     if (ws_bytes < L.total) return TOPK_E_WORKSPACE;
     char *w = (char *)workspace;
-    BtArgs a{};
+    a = BtArgs{};
     a.keys = (const u32 *)keys;
     a.row_off = (const u64 *)row_off;
     a.k = k;
@@ -1002,22 +1027,32 @@ extern "C" int topk_select_batched_f32(topk_ctx *c, const float *keys, const uin
     a.order = (u32 *)(w + L.order);
     a.queue = (u32 *)(w + L.queue);
     a.seed = c->seed;
-    a.s_target = (u32)c->bt_s_target;
-    a.c_num = (u32)c->bt_c_num;
     a.attempts = (u32)c->bt_attempts;
     a.fast = (u32)c->bt_fast;
+    a.cls_lo = 0;
+    a.cls_hi = BT_NCLS - 1;
+    for (int i = 0; i < BT_NCLS; ++i) {
+        a.s_cls[i] = (u32)(c->bt_s_cls[i] >= 0 ? c->bt_s_cls[i] : c->bt_s_target);
+        a.c_cls[i] = (u32)(c->bt_c_cls[i] >= 0 ? c->bt_c_cls[i] : c->bt_c_num);
+    }
+    return TOPK_OK;
+}
+
+int bt_run(topk_ctx *c, const BtArgs &a, bool graph, hipStream_t stream)
+{
     if (hipSetDevice(c->device) != hipSuccess) return TOPK_E_HIP;
     const int grid = (int)(c->num_cu * c->bt_wg_per_cu);   // 4 fit on a CU (LDS, registers)
-    if (!(flags & TOPK_GRAPH))
-        return bt_enqueue(a, grid, stream) == hipSuccess ? TOPK_OK : TOPK_E_HIP;
+    if (!graph) return bt_enqueue(a, grid, stream) == hipSuccess ? TOPK_OK : TOPK_E_HIP;
 
     // one graph per distinct argument set: captured once, then replayed
     std::vector<uint64_t> key = {
-        (uint64_t)(uintptr_t)keys, (uint64_t)(uintptr_t)row_off, rows, (uint64_t)(uintptr_t)k,
-        (uint64_t)(uintptr_t)out_off, a.flags, (uint64_t)(uintptr_t)out_idx,
-        (uint64_t)(uintptr_t)kth_key, (uint64_t)(uintptr_t)kth_idx, (uint64_t)(uintptr_t)status,
-        (uint64_t)(uintptr_t)workspace, a.seed, a.s_target, a.c_num, a.attempts, a.fast,
+        (uint64_t)(uintptr_t)a.keys, (uint64_t)(uintptr_t)a.row_off, a.rows,
+        (uint64_t)(uintptr_t)a.k, (uint64_t)(uintptr_t)a.out_off, a.flags,
+        (uint64_t)(uintptr_t)a.out_idx, (uint64_t)(uintptr_t)a.kth_key,
+        (uint64_t)(uintptr_t)a.kth_idx, (uint64_t)(uintptr_t)a.status,
+        (uint64_t)(uintptr_t)a.order, a.seed, a.attempts, a.fast, a.cls_lo, a.cls_hi,
         (uint64_t)grid};
+    for (int i = 0; i < BT_NCLS; ++i) key.push_back(((uint64_t)a.s_cls[i] << 32) | a.c_cls[i]);
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
         if (!c->capture_stream &&
@@ -1039,4 +1074,107 @@ extern "C" int topk_select_batched_f32(topk_ctx *c, const float *keys, const uin
         it = c->graphs.emplace(key, ge).first;
     }
     return hipGraphLaunch(it->second, stream) == hipSuccess ? TOPK_OK : TOPK_E_HIP;
+}
+
+// Median of `reps` timed eager calls of the batch (ms), or a negative error.
+float bt_time(topk_ctx *c, const BtArgs &a, uint32_t reps, hipStream_t stream, hipEvent_t e0,
+              hipEvent_t e1)
+{
+    std::vector<float> t;
+    for (uint32_t i = 0; i < reps; ++i) {
+        if (hipEventRecord(e0, stream) != hipSuccess) return -1.0f;
+        if (bt_run(c, a, false, stream) != TOPK_OK) return -1.0f;
+        if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+            return -1.0f;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0f;
+        t.push_back(ms);
+    }
+    std::sort(t.begin(), t.end());
+    return t[t.size() / 2];
+}
+
+}  // namespace
+
+extern "C" int topk_select_batched_f32(topk_ctx *c, const float *keys, const uint64_t *row_off,
+                                       uint32_t rows, const uint32_t *k, const uint64_t *out_off,
+                                       uint32_t flags, uint32_t *out_idx, float *kth_key,
+                                       uint32_t *kth_idx, uint32_t *status, void *workspace,
+                                       size_t ws_bytes, hipStream_t stream)
+{
+    BtArgs a;
+    const int rc = bt_args(c, keys, row_off, rows, k, out_off, flags, out_idx, kth_key, kth_idx,
+                           status, workspace, ws_bytes, a);
+    if (rc != TOPK_OK) return rc;
+    return bt_run(c, a, (flags & TOPK_GRAPH) != 0, stream);
+}
+
+extern "C" int topk_tune_batched_f32(topk_ctx *c, const float *keys, const uint64_t *row_off,
+                                     uint32_t rows, const uint32_t *k, const uint64_t *out_off,
+                                     uint32_t flags, uint32_t *out_idx, float *kth_key,
+                                     uint32_t *kth_idx, uint32_t *status, void *workspace,
+                                     size_t ws_bytes, uint32_t reps, hipStream_t stream)
+{
+    BtArgs a;
+    int rc = bt_args(c, keys, row_off, rows, k, out_off, flags & ~(uint32_t)TOPK_GRAPH, out_idx,
+                     kth_key, kth_idx, status, workspace, ws_bytes, a);
+    if (rc != TOPK_OK) return rc;
+    if (reps == 0 || reps > 100) return TOPK_E_INVALID;
+    if (hipSetDevice(c->device) != hipSuccess) return TOPK_E_HIP;
+    // rows per length class, from the row offsets
+    std::vector<uint64_t> off(rows + 1);
+    if (hipStreamSynchronize(stream) != hipSuccess ||
+        hipMemcpy(off.data(), row_off, off.size() * sizeof(uint64_t), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+        return TOPK_E_HIP;
+    std::vector<uint32_t> per(BT_NCLS, 0);
+    for (uint32_t r = 0; r < rows; ++r) {
+        const uint64_t len = off[r + 1] - off[r];
+        const uint32_t cls = len == 0 ? 0u : 64u - (uint32_t)__builtin_clzll(len);
+        ++per[cls < (uint32_t)BT_NCLS ? cls : BT_NCLS - 1];
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return TOPK_E_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return TOPK_E_HIP; }
+    const int64_t s_cand[] = {256, 512, 1024, 2048};
+    const int64_t c_cand[] = {8, 12, 16, 24};
+    // classes holding rows of the sampling path (longer than BT_REG_KEYS)
+    const uint32_t first = 64u - (uint32_t)__builtin_clzll((uint64_t)BT_REG_KEYS);
+    for (uint32_t cls = first; cls < (uint32_t)BT_NCLS && rc == TOPK_OK; ++cls) {
+        if (!per[cls]) continue;
+        float best = -1.0f;
+        int64_t bs = c->bt_s_target, bc = c->bt_c_num;
+        for (int64_t sv : s_cand) {
+            for (int64_t cv : c_cand) {
+                BtArgs t = a;
+                t.cls_lo = t.cls_hi = cls;
+                t.s_cls[cls] = (u32)sv;
+                t.c_cls[cls] = (u32)cv;
+                const float ms = bt_time(c, t, reps, stream, e0, e1);
+                if (ms < 0.0f) { rc = TOPK_E_HIP; break; }
+                if (best < 0.0f || ms < best) { best = ms; bs = sv; bc = cv; }
+            }
+            if (rc != TOPK_OK) break;
+        }
+        c->bt_s_cls[cls] = bs;
+        c->bt_c_cls[cls] = bc;
+        a.s_cls[cls] = (u32)bs;
+        a.c_cls[cls] = (u32)bc;
+    }
+    // then the resident workgroups per CU over the whole batch
+    if (rc == TOPK_OK) {
+        const int64_t keep = c->bt_wg_per_cu;
+        float best = -1.0f;
+        int64_t bw = keep;
+        for (int64_t wv = 2; wv <= 4; ++wv) {
+            c->bt_wg_per_cu = wv;
+            const float ms = bt_time(c, a, reps, stream, e0, e1);
+            if (ms < 0.0f) { rc = TOPK_E_HIP; break; }
+            if (best < 0.0f || ms < best) { best = ms; bw = wv; }
+        }
+        c->bt_wg_per_cu = rc == TOPK_OK ? bw : keep;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }

@@ -3,9 +3,15 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
+#include <ctype.h>
+#include <errno.h>
+#include <stdio.h>
+
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/topk.h"
@@ -79,6 +85,50 @@ int plan_rounds(const topk_ctx *c, uint64_t n, uint64_t k, double *sizes, int ma
         if (nr <= (double)c->tail_max) break;
     }
     return r;
+}
+
+void set_defaults(topk_ctx *c)
+{
+    c->s_target = 4096;
+    c->c_num = 16;
+    c->t_fin = 16384;
+    c->r_max = 24;
+    c->r_fast = -1;
+    c->band_div = 4;
+    c->tail_max = 65536;
+    c->timing = 0;
+    c->bt_s_target = 1024;
+    c->bt_c_num = 12;
+    c->bt_wg_per_cu = 4;
+    c->bt_attempts = 4;
+    c->bt_fast = 1;
+    for (int i = 0; i < TOPK_BT_NCLS; ++i) c->bt_s_cls[i] = c->bt_c_cls[i] = -1;
+}
+
+// The tuning parameters (what topk_save_tuning writes), in a fixed order.
+struct ParamRef { const char *name; int64_t topk_ctx::*field; };
+const ParamRef TUNING[] = {
+    {"s_target", &topk_ctx::s_target}, {"c_num", &topk_ctx::c_num}, {"t_fin", &topk_ctx::t_fin},
+    {"r_max", &topk_ctx::r_max}, {"r_fast", &topk_ctx::r_fast}, {"band_div", &topk_ctx::band_div},
+    {"tail_max", &topk_ctx::tail_max}, {"bt_s_target", &topk_ctx::bt_s_target},
+    {"bt_c_num", &topk_ctx::bt_c_num}, {"bt_wg_per_cu", &topk_ctx::bt_wg_per_cu},
+    {"bt_attempts", &topk_ctx::bt_attempts}, {"bt_fast", &topk_ctx::bt_fast},
+};
+
+// "bt_s_target@C" / "bt_c_num@C": the override of row-length class C.
+int64_t *cls_param(topk_ctx *c, const char *name)
+{
+    const char *at = strchr(name, '@');
+    if (!at) return nullptr;
+    const size_t len = (size_t)(at - name);
+    int64_t *arr = nullptr;
+    if (len == 11 && strncmp(name, "bt_s_target", 11) == 0) arr = c->bt_s_cls;
+    else if (len == 8 && strncmp(name, "bt_c_num", 8) == 0) arr = c->bt_c_cls;
+    if (!arr || !at[1]) return nullptr;
+    char *end = nullptr;
+    const long cls = strtol(at + 1, &end, 10);
+    if (*end || cls < 0 || cls >= TOPK_BT_NCLS) return nullptr;
+    return arr + cls;
 }
 
 int check_device(int device, int *num_cu)
@@ -182,19 +232,7 @@ int topk_create(topk_ctx **out, int hip_device, uint64_t seed)
     if (!c) return TOPK_E_INVALID;
     c->device = hip_device;
     c->seed = seed;
-    c->s_target = 4096;
-    c->c_num = 16;
-    c->t_fin = 16384;
-    c->r_max = 24;
-    c->r_fast = -1;
-    c->band_div = 4;
-    c->tail_max = 65536;
-    c->timing = 0;
-    c->bt_s_target = 1024;
-    c->bt_c_num = 24;
-    c->bt_wg_per_cu = 4;
-    c->bt_attempts = 4;
-    c->bt_fast = 1;
+    set_defaults(c);
     c->num_cu = ncu;
     *out = c;
     return TOPK_OK;
@@ -228,6 +266,14 @@ int topk_set_param(topk_ctx *c, const char *name, int64_t v)
         {"bt_fast", &c->bt_fast, 0, 1},
     };
     if (strcmp(name, "seed") == 0) { c->seed = (uint64_t)v; return TOPK_OK; }
+    int64_t *cls = cls_param(c, name);
+    if (cls) {
+        // -1 removes the override; otherwise the range of the global parameter
+        const bool s = name[3] == 's';
+        if (v != -1 && (v < (s ? 64 : 4) || v > (s ? 2048 : 4096))) return TOPK_E_INVALID;
+        *cls = v;
+        return TOPK_OK;
+    }
     for (auto &e : tab) {
         if (strcmp(name, e.n) == 0) {
             if (v < e.lo || v > e.hi) return TOPK_E_INVALID;
@@ -242,6 +288,7 @@ int topk_get_param(const topk_ctx *c, const char *name, int64_t *v)
 {
     if (!c || !name || !v) return TOPK_E_INVALID;
     if (strcmp(name, "seed") == 0) { *v = (int64_t)c->seed; return TOPK_OK; }
+    if (const int64_t *cls = cls_param(const_cast<topk_ctx *>(c), name)) { *v = *cls; return TOPK_OK; }
     const struct { const char *n; int64_t val; } tab[] = {
         {"s_target", c->s_target}, {"c_num", c->c_num}, {"t_fin", c->t_fin},
         {"r_max", c->r_max}, {"r_fast", c->r_fast}, {"band_div", c->band_div},
@@ -332,6 +379,103 @@ int topk_kernel_times(topk_ctx *c, float *ms, int32_t *kind, uint32_t max, uint3
     *count = m;
     c->ev_used = 0;
     return TOPK_OK;
+}
+
+int topk_save_tuning(const topk_ctx *c, const char *path)
+{
+    if (!c || !path) return TOPK_E_INVALID;
+    FILE *f = fopen(path, "w");
+    if (!f) return TOPK_E_INVALID;
+    bool first = true;
+    auto put = [&](const char *name, int64_t v) {
+        fprintf(f, "%s\n  \"%s\": %lld", first ? "{" : ",", name, (long long)v);
+        first = false;
+    };
+    for (const ParamRef &p : TUNING) put(p.name, c->*p.field);
+    char name[32];
+    for (int i = 0; i < TOPK_BT_NCLS; ++i) {
+        if (c->bt_s_cls[i] >= 0) { snprintf(name, sizeof name, "bt_s_target@%d", i); put(name, c->bt_s_cls[i]); }
+        if (c->bt_c_cls[i] >= 0) { snprintf(name, sizeof name, "bt_c_num@%d", i); put(name, c->bt_c_cls[i]); }
+    }
+    fprintf(f, "%s\n}\n", first ? "{" : "");
+    const bool ok = fclose(f) == 0;
+    return ok ? TOPK_OK : TOPK_E_INVALID;
+}
+
+int topk_load_tuning(topk_ctx *c, const char *path)
+{
+    if (!c) return TOPK_E_INVALID;
+    if (!path) {
+        const int64_t tm = c->timing;
+        set_defaults(c);
+        c->timing = tm;
+        return TOPK_OK;
+    }
+    FILE *f = fopen(path, "r");
+    if (!f) return TOPK_E_INVALID;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+    fclose(f);
+    // a flat JSON object of "name": integer pairs
+    std::vector<std::pair<std::string, int64_t>> kv;
+    size_t i = 0;
+    auto ws = [&]() { while (i < text.size() && isspace((unsigned char)text[i])) ++i; };
+    ws();
+    if (i >= text.size() || text[i] != '{') return TOPK_E_INVALID;
+    ++i;
+    ws();
+    if (i < text.size() && text[i] == '}') {
+        ++i;
+    } else {
+        for (;;) {
+            ws();
+            if (i >= text.size() || text[i] != '"') return TOPK_E_INVALID;
+            const size_t e = text.find('"', i + 1);
+            if (e == std::string::npos) return TOPK_E_INVALID;
+            std::string name = text.substr(i + 1, e - i - 1);
+            i = e + 1;
+            ws();
+            if (i >= text.size() || text[i] != ':') return TOPK_E_INVALID;
+            ++i;
+            ws();
+            char *end = nullptr;
+            errno = 0;
+            const long long v = strtoll(text.c_str() + i, &end, 10);
+            if (end == text.c_str() + i || errno) return TOPK_E_INVALID;
+            i = (size_t)(end - text.c_str());
+            kv.emplace_back(name, (int64_t)v);
+            ws();
+            if (i < text.size() && text[i] == ',') { ++i; continue; }
+            if (i < text.size() && text[i] == '}') { ++i; break; }
+            return TOPK_E_INVALID;
+        }
+    }
+    ws();
+    if (i != text.size()) return TOPK_E_INVALID;
+    // all or nothing: apply to a copy of the parameters, then keep them
+    topk_ctx *t = new (std::nothrow) topk_ctx;
+    if (!t) return TOPK_E_INVALID;
+    for (const ParamRef &p : TUNING) t->*p.field = c->*p.field;
+    memcpy(t->bt_s_cls, c->bt_s_cls, sizeof t->bt_s_cls);
+    memcpy(t->bt_c_cls, c->bt_c_cls, sizeof t->bt_c_cls);
+    t->seed = c->seed;
+    t->timing = c->timing;
+    int rc = TOPK_OK;
+    for (auto &p : kv) {
+        if (p.first == "seed" || p.first == "timing" || topk_set_param(t, p.first.c_str(), p.second) != TOPK_OK) {
+            rc = TOPK_E_INVALID;
+            break;
+        }
+    }
+    if (rc == TOPK_OK) {
+        for (const ParamRef &p : TUNING) c->*p.field = t->*p.field;
+        memcpy(c->bt_s_cls, t->bt_s_cls, sizeof c->bt_s_cls);
+        memcpy(c->bt_c_cls, t->bt_c_cls, sizeof c->bt_c_cls);
+    }
+    delete t;
+    return rc;
 }
 
 const char *topk_strerror(int code)

@@ -7,6 +7,10 @@
 #include <tuple>
 #include <vector>
 
+// Row-length classes of the batched form: class c holds the rows of length
+// [2^(c-1), 2^c) (class 0: empty rows, the last class: everything longer).
+constexpr int TOPK_BT_NCLS = 34;
+
 struct topk_ctx {
     int device;
     uint64_t seed;
@@ -14,6 +18,8 @@ struct topk_ctx {
     // batched form: sample size of a long row, pivot spread, workgroups per CU,
     // sampling attempts before the exact fallback, fast sweep on/off
     int64_t bt_s_target, bt_c_num, bt_wg_per_cu, bt_attempts, bt_fast;
+    // per row-length class overrides of bt_s_target / bt_c_num (-1: none)
+    int64_t bt_s_cls[TOPK_BT_NCLS], bt_c_cls[TOPK_BT_NCLS];
     int num_cu;
     // kernel timing: event pairs recorded by calls since the last read-out
     std::vector<hipEvent_t> ev;
