@@ -204,6 +204,17 @@ def bench_batched(args):
     off = torch.from_numpy(off_np.astype(np.int64)).to(dev)
     kk = torch.from_numpy(k_np.astype(np.int32)).to(dev)
     ctx = tk.Context(0, seed=0x5EED)
+    tuned = {}
+    if not args.no_tune:
+        # the autotuner (setup, untimed): sample size and spread per length
+        # class of the sampling path, workgroups per CU
+        ctx.tune_batched(keys, off, kk, reps=3)
+        for c in range(34):
+            sv = ctx.get_param("bt_s_target@%d" % c)
+            if sv >= 0:
+                tuned["class_%d" % c] = {"bt_s_target": sv, "bt_c_num": ctx.get_param("bt_c_num@%d" % c)}
+        tuned["bt_wg_per_cu"] = ctx.get_param("bt_wg_per_cu")
+        log("tuned: %s" % tuned)
     out = ctx.select_batched(keys, off, kk, graph=True)
     for _ in range(max(1, args.warmup)):
         out = ctx.select_batched(keys, off, kk, graph=True, out=out)
@@ -241,6 +252,7 @@ def bench_batched(args):
                         "clipped to [64, 2^20]), k ~ U{1..min(len, 2048)}, seed 4; one hipGraph "
                         "launch per step",
             "rows": R, "keys": total, "sum_k": sum_k, "ms": round(ms, 4),
+            "tuned": tuned or None,
             "gkeys_s": round(total / (ms * 1e-3) / 1e9, 2),
             "hbm_frac_min_bytes": round(b_min / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
             "per_row_loop": {"ms_est": round(loop_ms, 2), "rows_timed": len(rows),
@@ -292,6 +304,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batched form with the default parameters (no autotuner run)")
     ap.add_argument("--single-only", action="store_true",
                     help="only the single-instance selection (skip the batched and row forms)")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -133,7 +133,8 @@ __device__ void bt_select(SRC src, u32 n, int top, const u64 rank_in[2], const b
     u64 rank[2] = {rank_in[0], rank_in[1]};
     bool done[2] = {!act[0], !act[1]};
     res[0] = res[1] = 0ull;
-    for (u32 i = tid; i < BT_BINS; i += BT_THREADS) sh.hist[i] = 0u;
+    // every histogram bin is zero on entry (all users leave it so); the
+    // candidate counters are first used after the first pass's barriers
     if (tid < 2) sh.ccount[tid] = 0u;
     if (top >= 64) {
         // pref's bits at or above `top` are those of any pair
@@ -143,7 +144,6 @@ __device__ void bt_select(SRC src, u32 n, int top, const u64 rank_in[2], const b
         const u64 x0 = n ? src(0) : 0ull;
         pref[0] = pref[1] = top <= 0 ? x0 : (x0 >> top) << top;
     }
-    __syncthreads();
     for (int pass = 0; pass < 16 && !(done[0] && done[1]); ++pass) {
         int sh_[2];
 #pragma unroll
@@ -444,9 +444,8 @@ __device__ __forceinline__ u64 bt_band_tau(SRC ssrc, const u32 (&cnt)[BT_WAVES],
         const u32 b = 1u + ((o - ordL) >> shift);
         return b < BT_BINS - 1 ? b : BT_BINS - 1;
     };
-    for (u32 i = tid; i < BT_BINS; i += BT_THREADS) sh.hist[i] = 0u;
+    // every histogram bin is zero on entry (all users leave it so)
     if (tid == 0) sh.ccount[0] = 0u;
-    __syncthreads();
     u32 below = 0;
 #pragma unroll
     for (int v = 0; v < BT_WAVES; ++v) {
