@@ -205,16 +205,22 @@ def bench_batched(args):
     kk = torch.from_numpy(k_np.astype(np.int32)).to(dev)
     ctx = tk.Context(0, seed=0x5EED)
     tuned = {}
-    if not args.no_tune:
+    if args.tuning:
+        ctx.load_tuning(args.tuning)
+        log("tuning loaded from %s" % args.tuning)
+    elif not args.no_tune:
         # the autotuner (setup, untimed): sample size and spread per length
         # class of the sampling path, workgroups per CU
         ctx.tune_batched(keys, off, kk, reps=3)
+    if args.tuning or not args.no_tune:
         for c in range(34):
             sv = ctx.get_param("bt_s_target@%d" % c)
             if sv >= 0:
                 tuned["class_%d" % c] = {"bt_s_target": sv, "bt_c_num": ctx.get_param("bt_c_num@%d" % c)}
         tuned["bt_wg_per_cu"] = ctx.get_param("bt_wg_per_cu")
         log("tuned: %s" % tuned)
+        if args.save_tuning:
+            ctx.save_tuning(args.save_tuning)
     out = ctx.select_batched(keys, off, kk, graph=True)
     for _ in range(max(1, args.warmup)):
         out = ctx.select_batched(keys, off, kk, graph=True, out=out)
@@ -306,6 +312,12 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="batched form with the default parameters (no autotuner run)")
+    ap.add_argument("--tuning", metavar="FILE",
+                    help="batched form: load this tuning file instead of running the autotuner")
+    ap.add_argument("--save-tuning", metavar="FILE",
+                    help="batched form: write the parameters it ran with to FILE")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched form (no JSON line: a profiling aid)")
     ap.add_argument("--single-only", action="store_true",
                     help="only the single-instance selection (skip the batched and row forms)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -324,6 +336,9 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 2^30 bytes read, 2^30 bytes written")
         del src, dst
+    if args.batched_only:
+        log("batched: %s" % json.dumps(bench_batched(args)))
+        return
     out = bench_select(args)
     if not args.single_only:
         out["batched"] = bench_batched(args)
