@@ -32,6 +32,10 @@
 // order; general form: the part below L, then the rest, each in column order;
 // fast form: wave by wave, each wave's columns ascending);
 // kth_key[r] / kth_idx[r] the pair of rank k (key bits as stored).
+//
+// The waves of a workgroup exchange data only through LDS, so every barrier
+// of k_batched orders LDS alone (lds_sync): output stores and key loads stay
+// in flight across it.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -163,7 +167,7 @@ __device__ void bt_select(SRC src, u32 n, int top, const u64 rank_in[2], const b
                 if (!done[t] && bt_match(x, pref[t], lowb[t]))
                     atomicAdd(&sh.hist[(u32)(x >> sh_[t]) & (BT_BINS - 1)], t == 0 ? 1u : 65536u);
         }
-        __syncthreads();
+        lds_sync();
         // (2) scan: thread t covers bins [BT_BPT t, BT_BPT t + BT_BPT)
         u32 c[BT_BPT], csum = 0;
 #pragma unroll
@@ -173,7 +177,7 @@ __device__ void bt_select(SRC src, u32 n, int top, const u64 rank_in[2], const b
             csum += c[q];
         }
         u32 tot;
-        u32 before = block_excl_scan<BT_THREADS>(csum, sh.scan, &tot);
+        u32 before = block_excl_scan<BT_THREADS, true>(csum, sh.scan, &tot);
 #pragma unroll
         for (int q = 0; q < BT_BPT; ++q) {
 #pragma unroll
@@ -189,7 +193,7 @@ __device__ void bt_select(SRC src, u32 n, int top, const u64 rank_in[2], const b
             }
             before += c[q];
         }
-        __syncthreads();
+        lds_sync();
         bool gather[2] = {false, false};
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
@@ -218,7 +222,7 @@ __device__ void bt_select(SRC src, u32 n, int top, const u64 rank_in[2], const b
                     if (gather[t] && bt_match(x, pref[t], lowb[t]))
                         sh.cand[t][atomicAdd(&sh.ccount[t], 1u)] = x;
             }
-            __syncthreads();
+            lds_sync();
             if (w < 2 && gather[w]) {
                 const u32 m = sh.ccount[w];
                 const u64 mine = lane < m ? sh.cand[w][lane] : ~0ull;
@@ -231,7 +235,7 @@ __device__ void bt_select(SRC src, u32 n, int top, const u64 rank_in[2], const b
                 }
                 if (lane < m && (u64)below == rank[w]) sh.found[w] = mine;
             }
-            __syncthreads();
+            lds_sync();
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
                 if (!gather[t]) continue;
@@ -239,7 +243,7 @@ __device__ void bt_select(SRC src, u32 n, int top, const u64 rank_in[2], const b
                 done[t] = true;
             }
             if (tid < 2) sh.ccount[tid] = 0u;
-            __syncthreads();
+            lds_sync();
         }
     }
 }
@@ -266,7 +270,7 @@ __device__ void bt_emit(SRC src, u32 n, u64 tau, u32 *out, u32 limit, BtShared &
             c += (u32)__popcll(ballot(t));
         }
         if (lane == 0) sh.scan[w] = c;
-        __syncthreads();
+        lds_sync();
         u32 pos = cur, tot = 0;
 #pragma unroll
         for (int v = 0; v < BT_WAVES; ++v) {
@@ -285,7 +289,7 @@ __device__ void bt_emit(SRC src, u32 n, u64 tau, u32 *out, u32 limit, BtShared &
             pos += (u32)__popcll(m);
         }
         cur += tot;
-        __syncthreads();            // sh.scan is rewritten by the next step
+        lds_sync();            // sh.scan is rewritten by the next step
     }
 }
 
@@ -457,7 +461,7 @@ __device__ __forceinline__ u64 bt_band_tau(SRC ssrc, const u32 (&cnt)[BT_WAVES],
         }
     }
     if (lane == 0 && below) atomicAdd(&sh.hist[0], below);
-    __syncthreads();
+    lds_sync();
     u32 c[BT_BPT], csum = 0;
 #pragma unroll
     for (int q = 0; q < BT_BPT; ++q) {
@@ -466,7 +470,7 @@ __device__ __forceinline__ u64 bt_band_tau(SRC ssrc, const u32 (&cnt)[BT_WAVES],
         csum += c[q];
     }
     u32 tot;
-    u32 before = block_excl_scan<BT_THREADS>(csum, sh.scan, &tot);
+    u32 before = block_excl_scan<BT_THREADS, true>(csum, sh.scan, &tot);
 #pragma unroll
     for (int q = 0; q < BT_BPT; ++q) {
         if (before <= rank && rank < before + c[q]) {
@@ -476,12 +480,12 @@ __device__ __forceinline__ u64 bt_band_tau(SRC ssrc, const u32 (&cnt)[BT_WAVES],
         }
         before += c[q];
     }
-    __syncthreads();
+    lds_sync();
     const u32 b = __builtin_amdgcn_readfirstlane(sh.sel_bin[0]);
     const u32 nb = __builtin_amdgcn_readfirstlane(sh.sel_count[0]);
     const u32 rr = rank - __builtin_amdgcn_readfirstlane(sh.sel_before[0]);
     if (nb > (u32)WAVE) {
-        __syncthreads();
+        lds_sync();
         const u64 rk[2] = {(u64)rank, 0ull};
         const bool one[2] = {true, false};
         u64 t2[2];
@@ -495,7 +499,7 @@ __device__ __forceinline__ u64 bt_band_tau(SRC ssrc, const u32 (&cnt)[BT_WAVES],
             if (bin(x) == b) sh.cand[0][atomicAdd(&sh.ccount[0], 1u)] = x;
         }
     }
-    __syncthreads();
+    lds_sync();
     if (w == 0) {
         const u64 mine = lane < nb ? sh.cand[0][lane] : ~0ull;
         const u32 mlo = (u32)mine, mhi = (u32)(mine >> 32);
@@ -507,7 +511,7 @@ __device__ __forceinline__ u64 bt_band_tau(SRC ssrc, const u32 (&cnt)[BT_WAVES],
         }
         if (lane < nb && lt == rr) sh.found[0] = mine;
     }
-    __syncthreads();
+    lds_sync();
     return sh.found[0];
 }
 
@@ -545,7 +549,7 @@ __device__ __forceinline__ u64 bt_reg_select(const u32 (&o)[M], u32 n, u32 rank,
                 }
             }
         }
-        __syncthreads();
+        lds_sync();
         u32 c[BT_BPT], csum = 0;
 #pragma unroll
         for (int q = 0; q < BT_BPT; ++q) {
@@ -554,7 +558,7 @@ __device__ __forceinline__ u64 bt_reg_select(const u32 (&o)[M], u32 n, u32 rank,
             csum += c[q];
         }
         u32 tot;
-        u32 before = block_excl_scan<BT_THREADS>(csum, sh.scan, &tot);
+        u32 before = block_excl_scan<BT_THREADS, true>(csum, sh.scan, &tot);
 #pragma unroll
         for (int q = 0; q < BT_BPT; ++q) {
             if (before <= rk && rk < before + c[q]) {
@@ -564,7 +568,7 @@ __device__ __forceinline__ u64 bt_reg_select(const u32 (&o)[M], u32 n, u32 rank,
             }
             before += c[q];
         }
-        __syncthreads();
+        lds_sync();
         const u64 bsel = (u64)__builtin_amdgcn_readfirstlane(sh.sel_bin[0]) << sh_;
         cnt = __builtin_amdgcn_readfirstlane(sh.sel_count[0]);
         rk -= __builtin_amdgcn_readfirstlane(sh.sel_before[0]);
@@ -574,7 +578,7 @@ __device__ __forceinline__ u64 bt_reg_select(const u32 (&o)[M], u32 n, u32 rank,
     }
     if (lowb == 0) return ((u64)ph << 32) | pl;     // every bit fixed: that pair
     if (tid == 0) sh.ccount[0] = 0u;
-    __syncthreads();
+    lds_sync();
 #pragma unroll
     for (int j = 0; j < M; ++j) {
         if ((u32)j < jn) {
@@ -582,7 +586,7 @@ __device__ __forceinline__ u64 bt_reg_select(const u32 (&o)[M], u32 n, u32 rank,
             if (col < n && match(o[j], col)) sh.cand[0][atomicAdd(&sh.ccount[0], 1u)] = pack(o[j], col);
         }
     }
-    __syncthreads();
+    lds_sync();
     if (w == 0) {
         const u64 mine = lane < cnt ? sh.cand[0][lane] : ~0ull;
         const u32 mlo = (u32)mine, mhi = (u32)(mine >> 32);
@@ -594,7 +598,7 @@ __device__ __forceinline__ u64 bt_reg_select(const u32 (&o)[M], u32 n, u32 rank,
         }
         if (lane < cnt && lt == rk) sh.found[0] = mine;
     }
-    __syncthreads();
+    lds_sync();
     return sh.found[0];
 }
 
@@ -621,7 +625,7 @@ __device__ __forceinline__ void bt_reg_emit(const u32 (&o)[M], u32 n, u64 tau, u
             if (lane == 0) sh.ecnt[j][w] = c;
         }
     }
-    __syncthreads();
+    lds_sync();
     u32 pos = 0;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
@@ -638,7 +642,7 @@ __device__ __forceinline__ void bt_reg_emit(const u32 (&o)[M], u32 n, u64 tau, u
             pos += all;
         }
     }
-    __syncthreads();                    // ecnt is reused
+    lds_sync();                    // ecnt is reused
 }
 
 // A row of at most M BT_THREADS keys, held in registers as key order words.
@@ -704,16 +708,19 @@ __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
         const u32 s_target = a.s_cls[cls];
         bool fast_ok = a.fast != 0u;    // until a fast sweep overflows its region
         for (u32 att = 0; att < a.attempts && !in_lds && !fast_done; ++att) {
-            // sample -> LDS, compacted
-            u32 pos[BT_SEG];
+            // sample -> LDS, compacted; the keys are loaded before the scan
+            // of the counts, so their latency overlaps its barriers
+            u32 pos[BT_SEG], sk[BT_SEG];
             const int cnt = bt_sample(tid, len, s_target, a.seed, att, r, pos);
+#pragma unroll
+            for (int j = 0; j < BT_SEG; ++j) sk[j] = j < cnt ? row[pos[j]] : 0u;
             u32 s;
-            const u32 at = block_excl_scan<BT_THREADS>((u32)cnt, sh.scan, &s);
+            const u32 at = block_excl_scan<BT_THREADS, true>((u32)cnt, sh.scan, &s);
             s = __builtin_amdgcn_readfirstlane(s);
 #pragma unroll
             for (int j = 0; j < BT_SEG; ++j)
-                if (j < cnt) sh.buf[at + (u32)j] = gsrc(pos[j]);
-            __syncthreads();
+                if (j < cnt) sh.buf[at + (u32)j] = pack(key_ord<true, LARGEST>(sk[j]), pos[j]);
+            lds_sync();
             i64 lo, hi;
             pivot_ranks(s, k, len, c_num, lo, hi);
             const bool hl = lo >= 0, hr = hi < (i64)s;
@@ -730,7 +737,7 @@ __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
                 (u64)(hi + 1) * len * BT_FAST_DEN <= (u64)s * BT_FAST_NUM * BT_CAP) {
                 // fast sweep: candidates (<= R) into per-wave regions of sh.buf
                 const u32 wv = __builtin_amdgcn_readfirstlane(tid / WAVE), ln = tid & (WAVE - 1);
-                __syncthreads();
+                lds_sync();
                 u32 cw, aw;
                 u64 *reg = sh.buf + wv * BT_REG;
                 bt_fast_sweep<LARGEST>(row, len, hl ? ord_value<LARGEST>(oL) : 0.0f,
@@ -744,7 +751,7 @@ __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
                     sh.wt[0][wv] = cw;
                     sh.wt[1][wv] = aw;
                 }
-                __syncthreads();
+                lds_sync();
                 u32 n_ab = 0, n_a = 0, cnt[BT_WAVES];
                 bool over = false;
 #pragma unroll
@@ -764,7 +771,7 @@ __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
                     break;
                 }
                 fast_ok = false;             // region overflow: the general sweep, same pivots
-                __syncthreads();             // (it rewrites sh.wt, read above)
+                lds_sync();             // (it rewrites sh.wt, read above)
             }
             // one sweep: below L -> output, [L, R] -> LDS band.  Wave w takes
             // keys [s0 + 1024 w, s0 + 1024 w + 1024) of a step as 16 columns of
@@ -798,7 +805,7 @@ __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
                     }
                     const u32 par = st & 1u;
                     if (ln == 0) sh.wt[par][wv] = ta | (tb << 16);
-                    __syncthreads();
+                    lds_sync();
                     u32 pa = ca, pb = cb, sa = 0, sb = 0;
 #pragma unroll
                     for (int v = 0; v < BT_WAVES; ++v) {
@@ -827,7 +834,7 @@ __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
                     cb += sb;
                 }
             }
-            __syncthreads();
+            lds_sync();
             if (ca >= k || ca + cb < k) {
                 c_num *= 2;                  // the pivots missed rank k: wider
             } else if (cb > BT_CAP) {
@@ -866,7 +873,7 @@ __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
         a.kth_idx[r] = (u32)tau;
         a.kth_key[r] = (u32)tau < len ? row[(u32)tau] : 0u;
     }
-    __syncthreads();
+    lds_sync();
 }
 
 template <bool LARGEST>
@@ -874,14 +881,14 @@ __global__ __launch_bounds__(BT_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 {
     __shared__ BtShared sh;
     for (u32 i = threadIdx.x; i < BT_BINS; i += BT_THREADS) sh.hist[i] = 0u;
-    __syncthreads();
+    lds_sync();
     // rows in longest-first order from a queue: one row per grab for the first
     // BT_Q1 positions (the long rows), then BT_QCHUNK rows per grab
     for (;;) {
         if (threadIdx.x == 0) sh.next = atomicAdd(a.queue, 1u);
-        __syncthreads();
+        lds_sync();
         const u32 g = __builtin_amdgcn_readfirstlane(sh.next);
-        __syncthreads();
+        lds_sync();
         const u32 p0 = g < BT_Q1 ? g : BT_Q1 + (g - BT_Q1) * BT_QCHUNK;
         if (p0 >= a.rows) break;
         const u32 p1 = g < BT_Q1 ? p0 + 1 : (p0 + BT_QCHUNK < a.rows ? p0 + BT_QCHUNK : a.rows);

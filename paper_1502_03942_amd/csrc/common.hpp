@@ -126,14 +126,24 @@ __device__ __forceinline__ u64 wave_min_u64(u64 v) { return wave_ext_u64<false>(
 
 // Exclusive prefix sum over a workgroup of NT threads; returns this thread's
 // exclusive prefix and writes the total to *total.  `scratch` holds NT/64 u32.
-template <int NT>
+// Barrier that orders only LDS: waits for the wave's LDS operations, not for
+// its global loads and stores, which stay in flight across it.  For kernels
+// whose waves exchange data only through LDS.
+__device__ __forceinline__ void lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int NT, bool LDS_ONLY = false>
 __device__ __forceinline__ u32 block_excl_scan(u32 v, u32 *scratch, u32 *total)
 {
     constexpr int NW = NT / WAVE;
     const u32 w = threadIdx.x / WAVE, l = lane_id();
     u32 inc = wave_incl_scan(v);
     if (l == WAVE - 1) scratch[w] = inc;
-    __syncthreads();
+    if (LDS_ONLY) lds_sync(); else __syncthreads();
     u32 before = 0, tot = 0;
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
@@ -141,7 +151,7 @@ __device__ __forceinline__ u32 block_excl_scan(u32 v, u32 *scratch, u32 *total)
         before += (i < (int)w) ? s : 0u;
         tot += s;
     }
-    __syncthreads();
+    if (LDS_ONLY) lds_sync(); else __syncthreads();
     *total = tot;
     return before + inc - v;
 }
