@@ -656,7 +656,9 @@ __device__ __forceinline__ u64 bt_reg_row(const u32 *__restrict__ row, u32 len, 
 #pragma unroll
     for (int j = 0; j < M; ++j) {
         const u32 col = (u32)j * BT_THREADS + tid;
-        o[j] = (u32)j < jn && col < len ? row[col] : 0u;
+        // every load is issued before the first is used (a column past the
+        // row reads its last key; such slots are never counted)
+        o[j] = (u32)j < jn ? row[col < len ? col : len - 1] : 0u;
     }
 #pragma unroll
     for (int j = 0; j < M; ++j) o[j] = key_ord<true, LARGEST>(o[j]);
@@ -713,7 +715,7 @@ __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
             u32 pos[BT_SEG], sk[BT_SEG];
             const int cnt = bt_sample(tid, len, s_target, a.seed, att, r, pos);
 #pragma unroll
-            for (int j = 0; j < BT_SEG; ++j) sk[j] = j < cnt ? row[pos[j]] : 0u;
+            for (int j = 0; j < BT_SEG; ++j) sk[j] = row[j < cnt ? pos[j] : 0u];
             u32 s;
             const u32 at = block_excl_scan<BT_THREADS, true>((u32)cnt, sh.scan, &s);
             s = __builtin_amdgcn_readfirstlane(s);
@@ -786,7 +788,7 @@ __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
 #pragma unroll
                     for (int j = 0; j < 16; ++j) {
                         const u32 col = base + (u32)j * WAVE + ln;
-                        o[j] = col < len ? row[col] : 0u;
+                        o[j] = row[col < len ? col : len - 1];
                     }
                     u32 abits = 0, bbits = 0, ta = 0, tb = 0;
 #pragma unroll

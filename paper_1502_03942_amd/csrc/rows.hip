@@ -71,12 +71,19 @@ __global__ __launch_bounds__(RW_THREADS) void k_rows_fwd(const u32 *__restrict__
     const u64 row = blockIdx.x;
     const u32 *__restrict__ p = scores + row * N;
 
-    // element e of thread t is column e * 1024 + t (coalesced loads)
+    // element e of thread t is column e * 1024 + t (coalesced loads); every
+    // load is issued before the first is used (a column past the row reads
+    // the row's last key, then is marked empty)
     u32 o[IPT];
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
         const u32 col = (u32)e * RW_THREADS + tid;
-        o[e] = col < N ? key_ord<true, LARGEST>(__builtin_nontemporal_load(p + col)) : 0xFFFFFFFFu;
+        o[e] = __builtin_nontemporal_load(p + (col < N ? col : N - 1));
+    }
+#pragma unroll
+    for (int e = 0; e < IPT; ++e) {
+        const u32 col = (u32)e * RW_THREADS + tid;
+        o[e] = col < N ? key_ord<true, LARGEST>(o[e]) : 0xFFFFFFFFu;
     }
     auto comp = [&](int e) -> u64 {
         const u32 col = (u32)e * RW_THREADS + tid;

@@ -160,6 +160,32 @@ __device__ __forceinline__ u64 fetch_elem(const SelArgs &a, u32 src, u64 p)
     return pack(a.band_ord[src - 1][p], a.band_idx[src - 1][p]);
 }
 
+// v[j] = element p(j) of source src for every j < N, all loads issued before
+// the first is used (src uniform: one branch around the whole gather).
+template <bool IS_F32, bool LARGEST, int N, class POS>
+__device__ __forceinline__ void fetch_elems(const SelArgs &a, u32 src, POS p, u64 (&v)[N])
+{
+    src = __builtin_amdgcn_readfirstlane(src);
+    if (src == 0) {
+        u32 x[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) x[j] = a.keys[p(j)];
+#pragma unroll
+        for (int j = 0; j < N; ++j) v[j] = pack(key_ord<IS_F32, LARGEST>(x[j]), (u32)p(j));
+    } else {
+        const u32 *__restrict__ bo = a.band_ord[src - 1];
+        const u32 *__restrict__ bi = a.band_idx[src - 1];
+        u32 o[N], i[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            o[j] = bo[p(j)];
+            i[j] = bi[p(j)];
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j) v[j] = pack(o[j], i[j]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Sample and pivots (§2 "Bernoulli sampling", FR-selection; §4.1 samples the
 // current subproblem at rate s_target / n_cur).  Thread t owns segment t of
@@ -271,13 +297,22 @@ __device__ __forceinline__ void sample_and_pivot(const SelArgs &a, State *st, Sm
     } else {
         cnt = skip_sample(tid, n, a.s_target, a.seed, tag, pos);
     }
+    // every load is issued before the first is used: slots past cnt read an
+    // in-bounds element (the sample buffer holds S_MAX pairs; position 0
+    // exists) and are then marked empty
     u64 v[SEG_CAP];
+    if (collected) {
 #pragma unroll
-    for (int j = 0; j < SEG_CAP; ++j)
-        v[j] = j >= cnt ? ~0ull
-             : collected ? a.hs_buf[tid + (u32)j * PV_THREADS]
-             : pre ? a.hs_buf[tid * SEG_CAP + (u32)j]
-             : fetch_elem<IS_F32, LARGEST>(a, src, pos[j]);
+        for (int j = 0; j < SEG_CAP; ++j) v[j] = a.hs_buf[tid + (u32)j * PV_THREADS];
+    } else if (pre) {
+#pragma unroll
+        for (int j = 0; j < SEG_CAP; ++j) v[j] = a.hs_buf[tid * SEG_CAP + (u32)j];
+    } else {
+        fetch_elems<IS_F32, LARGEST, SEG_CAP>(
+            a, src, [&](int j) -> u64 { return j < cnt ? pos[j] : 0u; }, v);
+    }
+#pragma unroll
+    for (int j = 0; j < SEG_CAP; ++j) v[j] = j < cnt ? v[j] : ~0ull;
 
     u32 s_total;
     const u32 excl = block_excl_scan<PV_THREADS>((u32)cnt, sm.scan, &s_total);
@@ -347,10 +382,13 @@ __device__ __forceinline__ void finish(const SelArgs &a, State *st, Smem &sm)
     const u32 per = (n + PV_THREADS - 1) / PV_THREADS;
     const u64 b0 = (u64)tid * per;
     const int cnt = b0 >= n ? 0 : (int)((u64)n - b0 < per ? (u64)n - b0 : per);
+    // every load is issued before the first is used (slots past cnt read
+    // position n - 1, then are marked empty)
     u64 v[FIN_ITEMS];
+    fetch_elems<IS_F32, LARGEST, FIN_ITEMS>(
+        a, src, [&](int j) -> u64 { return j < cnt ? b0 + (u64)j : (u64)n - 1; }, v);
 #pragma unroll
-    for (int j = 0; j < FIN_ITEMS; ++j)
-        v[j] = j < cnt ? fetch_elem<IS_F32, LARGEST>(a, src, b0 + j) : ~0ull;
+    for (int j = 0; j < FIN_ITEMS; ++j) v[j] = j < cnt ? v[j] : ~0ull;
     const u64 ranks[2] = {(u64)k - 1, 0ull};
     const bool act[2] = {true, false};
     u64 tau2[2];
