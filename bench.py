@@ -74,19 +74,34 @@ def bench_select(args):
     log("generating %d f32 keys" % n)
     keys_np = synth.uniform_f32_grid(n, 2)
     keys = torch.from_numpy(keys_np).to(dev)
-    ctx = tk.Context(0, seed=0x5EED)
-    ws = {k: ctx.workspace(n) for k in ks}
-    ctx.set_param("timing", 1)
+    # one context per k: the autotuner (setup, untimed) picks s_target and
+    # c_num for each selection
+    ctxs = {k: tk.Context(0, seed=0x5EED) for k in ks}
+    ws = {k: ctxs[k].workspace(n) for k in ks}
+    tuned = {}
+    for k in ks:
+        if args.tuning_prefix:
+            ctxs[k].load_tuning(args.tuning_prefix + "single_k%d.json" % k)
+        elif not args.no_tune:
+            ctxs[k].tune(keys, k, reps=3, workspace=ws[k])
+        if args.save_tuning_prefix:
+            ctxs[k].save_tuning(args.save_tuning_prefix + "single_k%d.json" % k)
+        tuned[str(k)] = {"s_target": ctxs[k].get_param("s_target"),
+                         "c_num": ctxs[k].get_param("c_num")}
+        ctxs[k].set_param("timing", 1)
+    if args.tuning_prefix or not args.no_tune:
+        log("tuned: %s" % tuned)
     results = {}
 
     def step():
         for k in ks:
-            results[k] = ctx.select(keys, k, workspace=ws[k])
+            results[k] = ctxs[k].select(keys, k, workspace=ws[k])
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    ctx.kernel_times()                        # drop warm-up records
+    for k in ks:
+        ctxs[k].kernel_times()                # drop warm-up records
     log("warmup done; timing %d steps" % args.steps)
     per_k_ms = {k: 0.0 for k in ks}
     # whole-step time: events on the stream the library launches on
@@ -98,22 +113,24 @@ def bench_select(args):
     e0.record(stream)
     for _ in range(args.steps):
         for i, k in enumerate(ks):
-            results[k] = ctx.select(keys, k, workspace=ws[k])
+            results[k] = ctxs[k].select(keys, k, workspace=ws[k])
     e1.record(stream)
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
-    kt = ctx.kernel_times()
-    sweeps = [ms for kind, ms in kt if kind == "sweep_first"]
-    assert len(sweeps) == args.steps * len(ks), (len(sweeps), args.steps)
+    sweeps_k = {k: [ms for kind, ms in ctxs[k].kernel_times() if kind == "sweep_first"]
+                for k in ks}
+    sweeps = [ms for k in ks for ms in sweeps_k[k]]
+    assert all(len(sweeps_k[k]) == args.steps for k in ks), {k: len(v) for k, v in sweeps_k.items()}
     # per-k whole-call times (separate short pass, same launches)
     for i, k in enumerate(ks):
         ek[0].record(stream)
         for _ in range(args.steps):
-            ctx.select(keys, k, workspace=ws[k])
+            ctxs[k].select(keys, k, workspace=ws[k])
         ek[1].record(stream)
         torch.cuda.synchronize()
         per_k_ms[k] = ek[0].elapsed_time(ek[1]) / args.steps
-    ctx.kernel_times()
+    for k in ks:
+        ctxs[k].kernel_times()
 
     ms_per_step = total_ms / args.steps
     value = len(ks) * n / (ms_per_step * 1e-3) / 1e9
@@ -122,7 +139,7 @@ def bench_select(args):
     sweep_bytes = {}
     per_k = []
     for k in ks:
-        recs = ctx.trace_rounds(results[k])
+        recs = ctxs[k].trace_rounds(results[k])
         r0 = recs[0]
         sweep_bytes[k] = 4 * n + 4 * r0["na"] + 8 * r0["nb"]
         b_min = 4 * n + 4 * k
@@ -132,8 +149,7 @@ def bench_select(args):
             "hbm_frac_min_bytes": round(b_min / (per_k_ms[k] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
             "rounds": len(recs), "band1": r0["nb"], "below1": r0["na"],
         })
-    # sweeps are in enqueue order: step-major, k-minor
-    tot_bytes = sum(sweep_bytes[ks[i % len(ks)]] for i in range(len(sweeps)))
+    tot_bytes = sum(sweep_bytes[k] * len(sweeps_k[k]) for k in ks)
     tot_s = sum(sweeps) * 1e-3
     achieved = tot_bytes / tot_s / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -184,7 +200,8 @@ def bench_select(args):
                                "(2^-24 grid, seed 2), k in {2^10, 2^20, 2^27}, one step = "
                                "the three selections", "n": n, "k": list(ks),
                    "parallelism": "none (1 GPU)"},
-        "per_k": per_k, "roofline": roof, "cpu_baseline": cpu,
+        "per_k": per_k, "tuned": tuned if (args.tuning_prefix or not args.no_tune) else None,
+        "roofline": roof, "cpu_baseline": cpu,
     }
 
 
@@ -205,22 +222,22 @@ def bench_batched(args):
     kk = torch.from_numpy(k_np.astype(np.int32)).to(dev)
     ctx = tk.Context(0, seed=0x5EED)
     tuned = {}
-    if args.tuning:
-        ctx.load_tuning(args.tuning)
-        log("tuning loaded from %s" % args.tuning)
+    if args.tuning_prefix:
+        ctx.load_tuning(args.tuning_prefix + "batched.json")
+        log("tuning loaded from %sbatched.json" % args.tuning_prefix)
     elif not args.no_tune:
         # the autotuner (setup, untimed): sample size and spread per length
         # class of the sampling path, workgroups per CU
         ctx.tune_batched(keys, off, kk, reps=3)
-    if args.tuning or not args.no_tune:
+    if args.tuning_prefix or not args.no_tune:
         for c in range(34):
             sv = ctx.get_param("bt_s_target@%d" % c)
             if sv >= 0:
                 tuned["class_%d" % c] = {"bt_s_target": sv, "bt_c_num": ctx.get_param("bt_c_num@%d" % c)}
         tuned["bt_wg_per_cu"] = ctx.get_param("bt_wg_per_cu")
         log("tuned: %s" % tuned)
-        if args.save_tuning:
-            ctx.save_tuning(args.save_tuning)
+        if args.save_tuning_prefix:
+            ctx.save_tuning(args.save_tuning_prefix + "batched.json")
     out = ctx.select_batched(keys, off, kk, graph=True)
     for _ in range(max(1, args.warmup)):
         out = ctx.select_batched(keys, off, kk, graph=True, out=out)
@@ -312,10 +329,11 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="batched form with the default parameters (no autotuner run)")
-    ap.add_argument("--tuning", metavar="FILE",
-                    help="batched form: load this tuning file instead of running the autotuner")
-    ap.add_argument("--save-tuning", metavar="FILE",
-                    help="batched form: write the parameters it ran with to FILE")
+    ap.add_argument("--tuning-prefix", metavar="PREFIX",
+                    help="load the tuning files PREFIX{single_k<k>,batched}.json instead of "
+                         "running the autotuners")
+    ap.add_argument("--save-tuning-prefix", metavar="PREFIX",
+                    help="write the parameters each selection ran with to those files")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched form (no JSON line: a profiling aid)")
     ap.add_argument("--single-only", action="store_true",

@@ -158,6 +158,19 @@ int topk_trace_sample(const topk_ctx *ctx, const void *workspace, uint64_t n,
  * *count = kernels recorded (only min(count, max) are written). */
 int topk_kernel_times(topk_ctx *ctx, float *ms, int32_t *kind, uint32_t max, uint32_t *count);
 
+/* topk_tune_f32: the autotuner of the single-instance selection.  Same
+ * arguments as topk_select_f32 without out_keys and status (flags:
+ * TOPK_LARGEST only; the outputs are overwritten with valid results).  The
+ * call is timed (median of `reps` calls, HIP events on `stream`) under every
+ * pair "s_target" in {2048, 4096, 8192} x "c_num" in {8, 12, 16, 24}, and
+ * the fastest pair stays in ctx.  The workspace size does not depend on
+ * either parameter.  Blocks the host until the stream is idle.  Returns
+ * TOPK_OK, the errors of topk_select_f32, or TOPK_E_INVALID for reps outside
+ * 1..100. */
+int topk_tune_f32(topk_ctx *ctx, const float *keys, uint64_t n, uint64_t k, uint32_t flags,
+                  uint32_t *out_idx, float *kth_key, uint32_t *kth_idx, void *workspace,
+                  size_t ws_bytes, uint32_t reps, hipStream_t stream);
+
 /* ---- Batched selection: many rows of uneven length, each with its own k ----
  *
  * topk_select_batched_f32: for every row r of a CSR batch, the k[r] smallest

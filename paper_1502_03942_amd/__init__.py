@@ -74,6 +74,8 @@ def lib():
     L.topk_select_batched_f32.argtypes = [vp, vp, vp, u32, vp, vp, u32, vp, vp, vp, vp, vp, sz, vp]
     L.topk_tune_batched_f32.argtypes = [vp, vp, vp, u32, vp, vp, u32, vp, vp, vp, vp, vp, sz, u32, vp]
     L.topk_save_tuning.argtypes = [vp, ctypes.c_char_p]
+    L.topk_tune_f32.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_uint64, u32, vp, vp, vp, vp, sz,
+                                u32, vp]
     L.topk_load_tuning.argtypes = [vp, ctypes.c_char_p]
     L.topk_rows_fwd_f32.argtypes = [vp, vp, u32, u32, u32, u32, vp, vp, vp]
     L.topk_scatter_bwd_f32.argtypes = [vp, vp, u32, u32, u32, vp, vp]
@@ -151,7 +153,7 @@ class Context:
         out_idx = torch.empty(max(k, 1), dtype=torch.int32, device=dev)
         kth_key = torch.empty(1, dtype=keys.dtype, device=dev)
         kth_idx = torch.empty(1, dtype=torch.int32, device=dev)
-        status = torch.zeros(1, dtype=torch.int32, device=dev)
+        status = torch.empty(1, dtype=torch.int32, device=dev)     # every call writes it
         out_keys = torch.empty(max(k, 1), dtype=keys.dtype, device=dev) if write_keys else None
         if workspace is None:
             workspace = self.workspace(n, flags)
@@ -163,6 +165,24 @@ class Context:
         if write_keys:
             res["keys"] = out_keys[:k]
         return res
+
+    def tune(self, keys, k, largest=False, reps=3, workspace=None):
+        """Autotune s_target and c_num for this selection (topk_tune_f32, f32
+        keys); returns the output dict of a call with the chosen parameters."""
+        if keys.dtype != torch.float32 or keys.dim() != 1 or not keys.is_cuda:
+            raise TypeError("tune: keys must be a 1-D float32 CUDA tensor")
+        n = keys.numel()
+        flags = TOPK_LARGEST if largest else 0
+        if workspace is None:
+            workspace = self.workspace(n, flags)
+        dev = keys.device
+        out_idx = torch.empty(max(k, 1), dtype=torch.int32, device=dev)
+        kth_key = torch.empty(1, dtype=torch.float32, device=dev)
+        kth_idx = torch.empty(1, dtype=torch.int32, device=dev)
+        _check(lib().topk_tune_f32(self._h, _ptr(keys), n, k, flags, _ptr(out_idx), _ptr(kth_key),
+                                   _ptr(kth_idx), _ptr(workspace), workspace.numel(), int(reps),
+                                   _stream(dev)))
+        return self.select(keys, k, largest=largest, workspace=workspace)
 
     KERNEL_KINDS = ("pivot_first", "pivot", "sweep_first", "sweep", "tail")
 

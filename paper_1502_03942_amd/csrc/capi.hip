@@ -10,6 +10,7 @@
 #include <errno.h>
 #include <stdio.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -379,6 +380,57 @@ int topk_kernel_times(topk_ctx *c, float *ms, int32_t *kind, uint32_t max, uint3
     *count = m;
     c->ev_used = 0;
     return TOPK_OK;
+}
+
+int topk_tune_f32(topk_ctx *c, const float *keys, uint64_t n, uint64_t k, uint32_t flags,
+                  uint32_t *out_idx, float *kth_key, uint32_t *kth_idx, void *ws,
+                  size_t ws_bytes, uint32_t reps, hipStream_t stream)
+{
+    if (!c || reps == 0 || reps > 100) return TOPK_E_INVALID;
+    if (flags & ~(uint32_t)TOPK_LARGEST) return TOPK_E_INVALID;
+    // the workspace size does not depend on s_target or c_num
+    auto call = [&]() {
+        return select_common(c, (const uint32_t *)keys, n, k, flags, out_idx, nullptr,
+                             (uint32_t *)kth_key, kth_idx, nullptr, ws, ws_bytes, stream, true);
+    };
+    int rc = call();                    // argument checks, and a warm-up
+    if (rc != TOPK_OK) return rc;
+    if (hipSetDevice(c->device) != hipSuccess) return TOPK_E_HIP;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return TOPK_E_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return TOPK_E_HIP; }
+    const int64_t keep_s = c->s_target, keep_c = c->c_num;
+    const int64_t s_cand[] = {2048, 4096, 8192};
+    const int64_t c_cand[] = {8, 12, 16, 24};
+    float best = -1.0f;
+    int64_t bs = keep_s, bc = keep_c;
+    for (int64_t sv : s_cand) {
+        for (int64_t cv : c_cand) {
+            c->s_target = sv;
+            c->c_num = cv;
+            std::vector<float> t;
+            for (uint32_t i = 0; i < reps && rc == TOPK_OK; ++i) {
+                float ms = 0.0f;
+                if (hipEventRecord(e0, stream) != hipSuccess) rc = TOPK_E_HIP;
+                if (rc == TOPK_OK) rc = call();
+                if (rc == TOPK_OK && (hipEventRecord(e1, stream) != hipSuccess ||
+                                      hipEventSynchronize(e1) != hipSuccess ||
+                                      hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    rc = TOPK_E_HIP;
+                t.push_back(ms);
+            }
+            if (rc != TOPK_OK) break;
+            std::sort(t.begin(), t.end());
+            const float med = t[t.size() / 2];
+            if (best < 0.0f || med < best) { best = med; bs = sv; bc = cv; }
+        }
+        if (rc != TOPK_OK) break;
+    }
+    c->s_target = rc == TOPK_OK ? bs : keep_s;
+    c->c_num = rc == TOPK_OK ? bc : keep_c;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }
 
 int topk_save_tuning(const topk_ctx *c, const char *path)

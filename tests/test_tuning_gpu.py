@@ -80,3 +80,20 @@ def test_tuning_file_roundtrip(dev, tmp_path):
         a.set_param("bt_s_target@34", 512)
     with pytest.raises(tk.TopkError):
         a.set_param("bt_c_num@3", 2)
+
+
+def test_tune_single_keeps_results_exact(dev):
+    import torch
+    n = 1 << 22
+    keys_np = synth.normal_f32(n, 52)
+    keys = torch.from_numpy(keys_np).to(dev)
+    for k, largest in ((1000, False), (1 << 20, True)):
+        ctx = tk.Context(0, seed=17)
+        res = ctx.tune(keys, k, largest=largest, reps=1)
+        assert ctx.get_param("s_target") in (2048, 4096, 8192)
+        assert ctx.get_param("c_num") in (8, 12, 16, 24)
+        torch.cuda.synchronize()
+        assert int(res["status"].item()) == 0
+        got = res["idx"].cpu().numpy().view(np.uint32)
+        kb = int(res["kth_key"].cpu().numpy().view(np.uint32)[0])
+        assert oracle.check(keys_np, k, got, int(res["kth_idx"].item()), kb, largest) == 0
