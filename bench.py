@@ -205,6 +205,81 @@ def bench_select(args):
     }
 
 
+def bench_configs(args, c2_ms_per_k):
+    """The other single-instance configurations (u32 keys; parity-tested at the
+    same sizes), each timed with the default parameters (median of 10 calls;
+    the autotuner takes f32 keys), and the
+    bandwidth of a plain stream read of the 2^28 f32 array measured on the
+    same device, against which C2 is also reported."""
+    import torch
+    import paper_1502_03942_amd as tk
+    import synth
+
+    dev = torch.device("cuda:0")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps=10):
+        t = []
+        for _ in range(reps):
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            t.append(e0.elapsed_time(e1))
+        return float(np.median(t))
+
+    out = {}
+    # stream read: the library's plain read kernel (the first sweep's access
+    # pattern) over the 1 GiB array; torch reductions beside it for context
+    x = torch.from_numpy(synth.uniform_f32_grid(1 << 28, 2)).to(dev)
+    sink = torch.zeros(1, dtype=torch.int32, device=dev)
+    mctx = tk.Context(0)
+    probes = {"topk_stream_read": lambda: mctx.stream_read(x, sink),
+              "torch_sum": lambda: x.sum(), "torch_amax": lambda: torch.amax(x)}
+    gbs = {}
+    for name, fn in probes.items():
+        for _ in range(3):
+            fn()
+        gbs[name] = (1 << 30) / (timed(fn) * 1e-3) / 1e9
+    read_gbs = gbs["topk_stream_read"]
+    out["stream_read"] = {"how": "topk_stream_read over 2^28 f32 keys (1 GiB read once, "
+                                 "256-byte non-temporal column loads), median of 10",
+                          "gbs": round(read_gbs, 1),
+                          "probes_gbs": {k: round(v, 1) for k, v in gbs.items()}}
+    out["C2_frac_of_stream_read"] = {
+        str(k): round((4 * (1 << 28) + 4 * k) / (ms * 1e-3) / 1e9 / read_gbs, 4)
+        for k, ms in c2_ms_per_k.items()}
+    del x
+    cfgs = [
+        ("C1", "u32 n=2^20 uniform, seed 1", lambda: synth.uniform_u32(1 << 20, 1), 1000, False),
+        ("C3a", "u32 n=2^27 Zipf s=1.2 over 2^16 values, seed 3", lambda: synth.zipf_u32(1 << 27, 1.2, 1 << 16, 3), 1 << 20, False),
+        ("C3b", "C3a data, largest", None, 1 << 20, True),
+        ("C3c", "u32 n=2^27 all 2^31 but Bernoulli(0.01) uniform, seed 31", lambda: synth.all_equal_except(1 << 27, 0.01, 1 << 31, 31), 1 << 20, False),
+    ]
+    keys = None
+    for name, what, gen, k, largest in cfgs:
+        if gen is not None:
+            keys_np = gen()
+            keys = torch.from_numpy(keys_np.view(np.int32)).to(dev)
+        n = keys.numel()
+        ctx = tk.Context(0, seed=0x5EED)
+        ws = ctx.workspace(n)
+        for _ in range(2):
+            ctx.select(keys, k, largest=largest, workspace=ws)
+        ms = timed(lambda: ctx.select(keys, k, largest=largest, workspace=ws))
+        res = ctx.select(keys, k, largest=largest, workspace=ws)
+        torch.cuda.synchronize()
+        if int(res["status"].item()) != 0:
+            raise SystemExit("%s: status %d" % (name, int(res["status"].item())))
+        b_min = 4 * n + 4 * k
+        out[name] = {"workload": what, "n": n, "k": k, "largest": largest, "ms": round(ms, 4),
+                     "gkeys_s": round(n / (ms * 1e-3) / 1e9, 2),
+                     "hbm_frac_min_bytes": round(b_min / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+        log("%s: %.4f ms" % (name, ms))
+    return out
+
+
 def bench_batched(args):
     """The batched form on 65,536 lognormal rows (one graph launch per step),
     next to the plain per-row loop (topk_select_f32 per row) on a sample of
@@ -359,6 +434,7 @@ def main():
         return
     out = bench_select(args)
     if not args.single_only:
+        out["configs"] = bench_configs(args, {p["k"]: p["ms"] for p in out["per_k"]})
         out["batched"] = bench_batched(args)
         out["rows_topk"] = bench_rows(args)
     print(json.dumps(out), flush=True)

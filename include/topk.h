@@ -171,6 +171,16 @@ int topk_tune_f32(topk_ctx *ctx, const float *keys, uint64_t n, uint64_t k, uint
                   uint32_t *out_idx, float *kth_key, uint32_t *kth_idx, void *workspace,
                   size_t ws_bytes, uint32_t reps, hipStream_t stream);
 
+/* topk_stream_read: a measurement helper, not part of the selection.  Reads
+ * keys[0 .. n) once with the access pattern of the first sweep (wave-tiles of
+ * 64 columns x 64 lanes, 256-byte non-temporal loads, one 1024-thread
+ * workgroup per CU) and adds a word derived from them to *sink, so that the
+ * plain stream-read bandwidth of the device can be timed beside a selection.
+ * keys 256-byte aligned, n a positive multiple of 4096; asynchronous on
+ * `stream`.  Returns TOPK_OK, TOPK_E_INVALID or TOPK_E_HIP. */
+int topk_stream_read(topk_ctx *ctx, const uint32_t *keys, uint64_t n, uint32_t *sink,
+                     hipStream_t stream);
+
 /* ---- Batched selection: many rows of uneven length, each with its own k ----
  *
  * topk_select_batched_f32: for every row r of a CSR batch, the k[r] smallest

@@ -76,6 +76,7 @@ def lib():
     L.topk_save_tuning.argtypes = [vp, ctypes.c_char_p]
     L.topk_tune_f32.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_uint64, u32, vp, vp, vp, vp, sz,
                                 u32, vp]
+    L.topk_stream_read.argtypes = [vp, vp, ctypes.c_uint64, vp, vp]
     L.topk_load_tuning.argtypes = [vp, ctypes.c_char_p]
     L.topk_rows_fwd_f32.argtypes = [vp, vp, u32, u32, u32, u32, vp, vp, vp]
     L.topk_scatter_bwd_f32.argtypes = [vp, vp, u32, u32, u32, vp, vp]
@@ -183,6 +184,13 @@ class Context:
                                    _ptr(kth_idx), _ptr(workspace), workspace.numel(), int(reps),
                                    _stream(dev)))
         return self.select(keys, k, largest=largest, workspace=workspace)
+
+    def stream_read(self, keys, sink):
+        """One plain read of keys (1-D, 4-byte elements, numel a multiple of
+        4096) with the first sweep's access pattern (topk_stream_read): a
+        bandwidth reference, not a selection."""
+        _check(lib().topk_stream_read(self._h, _ptr(keys), keys.numel(), _ptr(sink),
+                                      _stream(keys.device)))
 
     KERNEL_KINDS = ("pivot_first", "pivot", "sweep_first", "sweep", "tail")
 

@@ -24,7 +24,8 @@ def test_header_declares_entry_points():
     for want in ("topk_create", "topk_destroy", "topk_select_u32", "topk_select_f32",
                  "topk_workspace_bytes", "topk_set_param", "topk_strerror",
                  "topk_rows_fwd_f32", "topk_scatter_bwd_f32", "topk_select_batched_f32",
-                 "topk_tune_batched_f32", "topk_save_tuning", "topk_load_tuning", "topk_tune_f32"):
+                 "topk_tune_batched_f32", "topk_save_tuning", "topk_load_tuning", "topk_tune_f32",
+                 "topk_stream_read"):
         assert want in names
 
 
