@@ -411,6 +411,8 @@ def main():
                     help="write the parameters each selection ran with to those files")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched form (no JSON line: a profiling aid)")
+    ap.add_argument("--rows-only", action="store_true",
+                    help="only the row-wise forward and backward (no JSON line: a profiling aid)")
     ap.add_argument("--single-only", action="store_true",
                     help="only the single-instance selection (skip the batched and row forms)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -431,6 +433,9 @@ def main():
         del src, dst
     if args.batched_only:
         log("batched: %s" % json.dumps(bench_batched(args)))
+        return
+    if args.rows_only:
+        log("rows: %s" % json.dumps(bench_rows(args)))
         return
     out = bench_select(args)
     if not args.single_only:
