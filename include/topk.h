@@ -59,14 +59,16 @@ extern "C" {
 
 /* Device status word bits (written by every select call when status != NULL). */
 #define TOPK_STATUS_OK 0u
-#define TOPK_STATUS_NO_CONVERGENCE 1u  /* attempt budget r_max spent; outputs invalid */
+#define TOPK_STATUS_INTERNAL 1u        /* an internal consistency check failed (a
+                                          library defect); outputs invalid          */
 #define TOPK_STATUS_BAD_ROW 2u         /* batched: some row had k = 0 or k > len      */
 
 typedef struct topk_ctx topk_ctx;
 
 /* Create a context on HIP device `hip_device` (must be gfx950).  `seed` keys
- * the counter-based random stream (Philox4x32-10) of the sampler: equal seeds
- * give equal samples, hence identical traces and output order.
+ * the counter-based random stream (Philox4x32-10) of the sampler.  The
+ * selected set, the k-th key and its position never depend on the seed or on
+ * any parameter; only the running time and the round trace do.
  * Returns TOPK_OK and *out, TOPK_E_INVALID (out NULL), TOPK_E_HIP or
  * TOPK_E_UNSUPPORTED. */
 int topk_create(topk_ctx **out, int hip_device, uint64_t seed);
@@ -80,7 +82,11 @@ void topk_destroy(topk_ctx *ctx);
  *                      m_hi (s - m_lo) / s)) + 1 (§2, FR-selection); 0..4096
  *   "t_fin"     16384  subproblems of at most this size are solved directly
  *                      in one workgroup (§2 base case); 1..16384
- *   "r_max"      24    attempt budget (rounds + repeated rounds); 1..32
+ *   "r_max"      24    sampling attempts (rounds + repeated rounds); 1..32.
+ *                      Once spent, the object of rank k of the remaining
+ *                      subproblem is found exactly by a streaming radix select
+ *                      (one workgroup) and the call finishes with it: every
+ *                      valid call terminates with the exact result
  *   "r_fast"     -1    multi-workgroup rounds enqueued before the single-
  *                      workgroup tail; -1 = chosen from n and k; 0..8
  *   "band_div"   4     the middle part b of a round may hold n/band_div + 65536
@@ -102,17 +108,16 @@ size_t topk_workspace_bytes(const topk_ctx *ctx, uint64_t n, uint32_t flags);
 /* Select the k smallest (largest with TOPK_LARGEST) of keys[0..n).
  *   keys      [n]  u32 or f32 keys
  *   n, k           1 <= k <= n < 2^32
- *   out_idx   [k]  positions of the selected keys.  Order: the positions
- *                  below each round's lower pivot, round by round, each run in
- *                  the order of the round's input (ascending position for the
- *                  first round), then the remaining selected positions of the
- *                  final small subproblem in that subproblem's order.  The
- *                  order is fixed by (keys, k, flags, parameters, seed).
+ *   out_idx   [k]  positions of the selected keys, each exactly once, in an
+ *                  unspecified order that may differ between calls (the
+ *                  sweeps hand out output ranges in the order their
+ *                  workgroups arrive); sort them for a canonical order
  *   out_keys  [k]  NULL, or (with TOPK_WRITE_KEYS) keys[out_idx[i]], bits as in
  *                  the input
  *   kth_key   [1]  the key of rank k (input bits, e.g. -0.0 and NaN payloads kept)
  *   kth_idx   [1]  its position; out_idx always contains it
- *   status    [1]  NULL or the device status word (TOPK_STATUS_*)
+ *   status    [1]  NULL or the device status word: TOPK_STATUS_OK, or
+ *                  TOPK_STATUS_INTERNAL if a consistency check failed
  *   workspace      >= topk_workspace_bytes(ctx, n, flags) bytes, 256-byte aligned
  * Returns TOPK_OK, TOPK_E_INVALID, TOPK_E_WORKSPACE or TOPK_E_HIP. */
 int topk_select_u32(topk_ctx *ctx, const uint32_t *keys, uint64_t n, uint64_t k,
@@ -125,7 +130,10 @@ int topk_select_f32(topk_ctx *ctx, const float *keys, uint64_t n, uint64_t k,
                     void *workspace, size_t ws_bytes, hipStream_t stream);
 
 /* One recorded round of the last select call that used `workspace`
- * (§2 Algorithm: sample, pivots l = S[lo] and r = S[hi], counts of a and b). */
+ * (§2 Algorithm: sample, pivots l = S[lo] and r = S[hi], counts of a and b).
+ * The exact fallback round (after r_max attempts) has s = 0 and
+ * lo = hi = TOPK_ROUND_EXACT: both pivots are the object of rank k_cur. */
+#define TOPK_ROUND_EXACT (-2)
 typedef struct topk_round_record {
     uint32_t n_cur, k_cur;   /* subproblem entering the round                    */
     uint32_t s;              /* sample size drawn                                 */
@@ -140,9 +148,9 @@ typedef struct topk_round_record {
 
 /* Copy the round records of the last select call out of `workspace` (device)
  * into `out` (host, room for `max` records); *count = rounds recorded.
- * Synchronises `stream`.  With TOPK_TRACE, *_trace_sample copies the sample
- * positions (indices into that round's input sequence, ascending) of attempt
- * `tag` into out_pos (host, room for `cap`); *count = sample size. */
+ * Synchronises `stream`.  With TOPK_TRACE, *_trace_sample copies the sampled
+ * objects (their input positions, in no particular order) of attempt `tag`
+ * into out_pos (host, room for `cap`); *count = sample size. */
 int topk_trace_rounds(const topk_ctx *ctx, const void *workspace, uint64_t n,
                       topk_round_record *out, uint32_t max, uint32_t *count,
                       hipStream_t stream);

@@ -20,44 +20,18 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _lib = None
 
 
-class Round(ctypes.Structure):
-    """One round of the replayed recursion (see ``orc_replay``)."""
-    _fields_ = [
-        ("n_cur", ctypes.c_uint32), ("k_cur", ctypes.c_uint32),
-        ("s", ctypes.c_uint32), ("c_num", ctypes.c_uint32),
-        ("lo", ctypes.c_int64), ("hi", ctypes.c_int64),
-        ("l_idx", ctypes.c_uint32), ("r_idx", ctypes.c_uint32),
-        ("has_l", ctypes.c_uint32), ("has_r", ctypes.c_uint32),
-        ("na", ctypes.c_uint32), ("nb", ctypes.c_uint32),
-        ("ok", ctypes.c_uint32), ("tag", ctypes.c_uint32),
-    ]
-
-    def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
-
-
-class Params(ctypes.Structure):
-    """Parameters of the sampling recursion replayed by ``replay``."""
-    _fields_ = [
-        ("s_target", ctypes.c_uint32), ("c_num", ctypes.c_uint32),
-        ("nseg", ctypes.c_uint32), ("seg_cap", ctypes.c_uint32),
-        ("t_fin", ctypes.c_uint32), ("r_max", ctypes.c_uint32),
-        ("band_cap", ctypes.c_uint64), ("seed", ctypes.c_uint64),
-        ("s_max", ctypes.c_uint32), ("pad", ctypes.c_uint32),
-    ]
-
-
 def lib():
     """Load liboracle.so, building it with gcc if it is missing."""
     global _lib
     if _lib is None:
         path = os.path.join(_HERE, "liboracle.so")
-        if not os.path.exists(path):
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
             _build.build()
         L = ctypes.CDLL(path)
         vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
         L.orc_select_sort.argtypes = [vp, i32, u64, u64, i32, vp]
         L.orc_select_brute.argtypes = [vp, i32, u64, u64, i32, vp, vp]
+        L.orc_select_composite.argtypes = [vp, i32, u64, u64, i32, i32, vp]
         L.orc_check.argtypes = [vp, i32, u64, u64, i32, vp, u32, u32]
         L.orc_precedes.argtypes = [vp, i32, i32, u32, u32]
         L.orc_philox4x32_10.argtypes = [vp, vp, vp]
@@ -66,11 +40,10 @@ def lib():
         L.orc_bernoulli_sample.restype = ctypes.c_int64
         L.orc_pivot_ranks.argtypes = [u64, u64, u64, u32, vp, vp]
         L.orc_pivot_ranks.restype = None
-        L.orc_replay.argtypes = [vp, i32, u64, u64, i32, ctypes.POINTER(Params), vp, vp,
-                                 ctypes.POINTER(Round), vp]
-        L.orc_hash_taken.argtypes = [u64, u32, u32, u64]
-        L.orc_band_threshold.argtypes = [u64, u64, ctypes.c_int64, ctypes.c_int64, u64]
-        L.orc_band_threshold.restype = u64
+        L.orc_rank.argtypes = [vp, i32, u64, i32, u32]
+        L.orc_rank.restype = u64
+        L.orc_rank_among.argtypes = [vp, i32, i32, vp, u64, vp, u64, vp]
+        L.orc_rank_among.restype = None
         _lib = L
     return _lib
 
@@ -99,6 +72,18 @@ def select_sort(keys, k, largest=False):
     rc = lib().orc_select_sort(_p(keys), f, keys.size, k, int(largest), _p(out))
     if rc != 0:
         raise ValueError("orc_select_sort rc=%d" % rc)
+    return out
+
+
+def select_composite(keys, k, largest=False, threads=1):
+    """The same selection by a sort of 64-bit composites (value order word,
+    position) on ``threads`` threads (chunk sorts, then a merge of the first k).
+    The form the benchmark times; returns the first k in the unique order."""
+    keys, f = _keys(keys)
+    out = np.empty(k, np.uint32)
+    rc = lib().orc_select_composite(_p(keys), f, keys.size, k, int(largest), int(threads), _p(out))
+    if rc != 0:
+        raise ValueError("orc_select_composite rc=%d" % rc)
     return out
 
 
@@ -163,32 +148,22 @@ def pivot_ranks(s, k, n, c_num):
     return lo.value, hi.value
 
 
-def hash_taken(seed, tag, x, T):
-    """Per-element Bernoulli decision of the sample drawn while b is formed (§2)."""
-    return bool(lib().orc_hash_taken(seed, tag, x, T))
-
-
-def band_threshold(n_cur, s, lo, hi, s_target):
-    """Rate (as T = rho 2^32) of the sample of the middle part b."""
-    return int(lib().orc_band_threshold(n_cur, s, lo, hi, s_target))
-
-
-def replay(keys, k, largest=False, *, s_target, c_num, nseg, seg_cap, t_fin, r_max,
-           band_cap, seed, s_max=16384):
-    """Step-by-step replay of the sampling selection (§2 Algorithm, §4.1).
-
-    Returns (status, out_idx[k] in the order the recursion writes them,
-    kth_idx, list of per-round dicts).
-    """
+def rank(keys, x, largest=False):
+    """Rank of object x: the number of objects preceding it in the unique order
+    (§2).  The k smallest are the objects of rank < k (§4); the counts |a| and
+    |b| of a round of the Algorithm of §2 are rank differences of its pivots."""
     keys, f = _keys(keys)
-    prm = Params(s_target, c_num, nseg, seg_cap, t_fin, r_max, band_cap, seed, s_max, 0)
-    out = np.zeros(k, np.uint32)
-    kth = np.zeros(1, np.uint32)
-    recs = (Round * max(r_max, 1))()
-    nrec = np.zeros(1, np.uint32)
-    rc = lib().orc_replay(_p(keys), f, keys.size, k, int(largest), ctypes.byref(prm),
-                          _p(out), _p(kth), recs, _p(nrec))
-    return rc, out, int(kth[0]), [recs[i].as_dict() for i in range(int(nrec[0]))]
+    return int(lib().orc_rank(_p(keys), f, keys.size, int(largest), int(x)))
+
+
+def rank_among(keys, xs, ys, largest=False):
+    """For each object of xs, the number of objects of ys preceding it (O(|xs| |ys|))."""
+    keys, f = _keys(keys)
+    xs = np.ascontiguousarray(xs, dtype=np.uint32)
+    ys = np.ascontiguousarray(ys, dtype=np.uint32)
+    out = np.empty(xs.size, np.uint64)
+    lib().orc_rank_among(_p(keys), f, int(largest), _p(xs), xs.size, _p(ys), ys.size, _p(out))
+    return out
 
 
 def topk_rows(scores, k):

@@ -11,19 +11,22 @@
  *   - the key order with the (value, object) tie rule          (§2, Preliminaries)
  *   - select by full sort                      ("plain" oracle, §4 problem statement)
  *   - select by brute-force rank counting      (pins the plain oracle on tiny inputs)
+ *   - select by a sort of 64-bit composites    (the same result; the form the benchmark
+ *                                               times, on one thread or several)
  *   - an O(n) checker of a claimed result      (invariants of the selection problem)
  *   - Philox4x32-10                             (Salmon et al., SC'11, published definition)
  *   - Bernoulli sampling with geometric skips  (§2, "Bernoulli sampling")
  *   - pivot ranks around k|S|/n ± Δ            (§2, distributed FR-selection; §4.1 proof)
- *   - a replay of the recursive three-way partition selection
- *                                               (§2, Algorithm "communication efficient
- *                                                selection"; §4.1, Theorem "selectFR")
+ *   - the rank of an object in the unique order  (§2 order, §4 problem statement): the
+ *                                               counts |a| and |b| of a round of the
+ *                                               Algorithm of §2 are rank differences
  *
  * All integer results are exact.  The only floating point is inside the skip
  * computation of the sampler (fp64 log), which decides sample positions only.
  */
 #define _GNU_SOURCE
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -118,6 +121,92 @@ int orc_select_brute(const void *keys, int is_f32, uint64_t n, uint64_t k,
         if (rank == k - 1) *kth_idx = (uint32_t)i;
     }
     return m == k ? 0 : -3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The same selection by a sort of 64-bit composites (value order word << 32 |
+ * position), whose unsigned order is the unique order of §2: the form the
+ * benchmark times.  The value order word of a float is its IEEE bit pattern
+ * made monotone: all NaNs map to the largest word, -0.0 to the word of +0.0,
+ * negative numbers to the complement of their bits, the others to their bits
+ * with the sign bit set.  `largest` complements the word (the position part
+ * stays ascending).  With `threads` > 1 the composites are cut into that many
+ * chunks, each sorted by its own thread, and the first k are merged. */
+static uint32_t orc_value_word(const void *keys, int is_f32, uint64_t i, int largest)
+{
+    uint32_t b = ((const uint32_t *)keys)[i];
+    uint32_t w;
+    if (!is_f32) {
+        w = b;
+    } else {
+        float f;
+        memcpy(&f, &b, 4);
+        if (isnan(f)) w = 0xFFFFFFFFu;
+        else if (f == 0.0f) w = 0x80000000u;
+        else if (b & 0x80000000u) w = ~b;
+        else w = b | 0x80000000u;
+    }
+    return largest ? ~w : w;
+}
+
+static int cmp_u64(const void *pa, const void *pb)
+{
+    uint64_t a = *(const uint64_t *)pa, b = *(const uint64_t *)pb;
+    return a < b ? -1 : a > b ? 1 : 0;
+}
+
+typedef struct {
+    const void *keys;
+    int is_f32, largest;
+    uint64_t *c;
+    uint64_t lo, hi;
+} orc_chunk;
+
+static void *orc_chunk_sort(void *arg)
+{
+    orc_chunk *ch = (orc_chunk *)arg;
+    for (uint64_t i = ch->lo; i < ch->hi; ++i)
+        ch->c[i] = ((uint64_t)orc_value_word(ch->keys, ch->is_f32, i, ch->largest) << 32) | i;
+    qsort(ch->c + ch->lo, ch->hi - ch->lo, sizeof(uint64_t), cmp_u64);
+    return NULL;
+}
+
+int orc_select_composite(const void *keys, int is_f32, uint64_t n, uint64_t k, int largest,
+                         int threads, uint32_t *out_idx)
+{
+    if (n == 0 || k == 0 || k > n || n > 0xFFFFFFFFull || threads < 1) return -1;
+    if ((uint64_t)threads > n) threads = (int)n;
+    uint64_t *c = (uint64_t *)malloc(n * sizeof(uint64_t));
+    orc_chunk *ch = (orc_chunk *)calloc((size_t)threads, sizeof(orc_chunk));
+    pthread_t *th = (pthread_t *)calloc((size_t)threads, sizeof(pthread_t));
+    uint64_t *head = (uint64_t *)calloc((size_t)threads, sizeof(uint64_t));
+    if (!c || !ch || !th || !head) { free(c); free(ch); free(th); free(head); return -2; }
+    for (int t = 0; t < threads; ++t) {
+        ch[t].keys = keys; ch[t].is_f32 = is_f32; ch[t].largest = largest; ch[t].c = c;
+        ch[t].lo = n * (uint64_t)t / (uint64_t)threads;
+        ch[t].hi = n * (uint64_t)(t + 1) / (uint64_t)threads;
+    }
+    int rc = 0;
+    if (threads == 1) {
+        orc_chunk_sort(&ch[0]);
+    } else {
+        int started = 0;
+        for (; started < threads; ++started)
+            if (pthread_create(&th[started], NULL, orc_chunk_sort, &ch[started]) != 0) break;
+        for (int t = 0; t < started; ++t) pthread_join(th[t], NULL);
+        if (started < threads) rc = -2;
+    }
+    /* merge the first k: repeatedly take the smallest chunk head */
+    for (int t = 0; t < threads && rc == 0; ++t) head[t] = ch[t].lo;
+    for (uint64_t m = 0; m < k && rc == 0; ++m) {
+        int best = -1;
+        for (int t = 0; t < threads; ++t)
+            if (head[t] < ch[t].hi && (best < 0 || c[head[t]] < c[head[best]])) best = t;
+        out_idx[m] = (uint32_t)c[head[best]];
+        ++head[best];
+    }
+    free(c); free(ch); free(th); free(head);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -284,186 +373,30 @@ void orc_pivot_ranks(uint64_t s, uint64_t k, uint64_t n, uint32_t c_num,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Bernoulli sample by per-element decisions (§2, "Bernoulli sampling": every
- * object is taken independently with probability rho).  Used for the sample of
- * a subproblem that is being produced element by element: object x (input
- * position) is taken iff word 0 of Philox4x32-10 at counter (x, 0, tag, 1)
- * with key = seed is below T = floor(rho 2^32) (T >= 2^32: every object). */
-int orc_hash_taken(uint64_t seed, uint32_t tag, uint32_t x, uint64_t T)
+/* Rank of an object: the number of objects that precede it in the unique
+ * order (§2).  The k smallest are exactly the objects of rank < k (§4), and a
+ * partition of the Algorithm of §2 by pivots l <= r (a = {e < l},
+ * b = {l <= e <= r}) has |a| = rank(l) and |b| = rank(r) - rank(l) + 1 within
+ * any interval of the order that holds both pivots.  O(n). */
+uint64_t orc_rank(const void *keys, int is_f32, uint64_t n, int largest, uint32_t x)
 {
-    uint32_t ctr[4] = {x, 0, tag, 1};
-    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
-    uint32_t out[4];
-    orc_philox4x32_10(ctr, key, out);
-    return (uint64_t)out[0] < T;
-}
-
-/* Rate of that sample for the middle part b of a round: the pivots cover the
- * sample ranks [bot, top) with bot = lo (0 without a lower pivot) and
- * top = hi + 1 (s without an upper pivot), so b is expected to hold about
- * n_cur (top - bot) / s elements; rho = s_target / that, as T = rho 2^32. */
-uint64_t orc_band_threshold(uint64_t n_cur, uint64_t s, int64_t lo, int64_t hi,
-                            uint64_t s_target)
-{
-    uint64_t nb_est = n_cur;
-    if (s > 0) {
-        int64_t bot = lo >= 0 ? lo : 0;
-        int64_t top = hi < (int64_t)s ? hi + 1 : (int64_t)s;
-        nb_est = n_cur * (uint64_t)(top - bot) / s;
-    }
-    if (nb_est == 0) nb_est = 1;
-    uint64_t T = (s_target << 32) / nb_est;
-    return T;
-}
-
-/* ------------------------------------------------------------------------ */
-/* Replay of the recursive selection (§2, Algorithm "communication efficient
- * selection", with the sampling of §4.1), step by step, on one address space.
- *
- * Round:  sample the current subproblem at rate s_target / n_cur; sort the
- * sample; pick pivots l = S[lo], r = S[hi]; partition the current sequence
- * into a = {e < l}, b = {l <= e <= r}, c = {e > r}; n_a = |a|, n_b = |b|.
- * Elements of a are written (in sequence order) to out_idx after the
- * `cursor` elements already fixed; b (in sequence order) becomes the next
- * subproblem; k_cur -= n_a.  A round is repeated on the same subproblem with
- * a fresh random stream when its pivots do not bracket rank k_cur (n_a >=
- * k_cur or n_a + n_b < k_cur; this replaces the recursion into a or c, with
- * the same result) -- then with c doubled -- or when b is too wide (more
- * than band_cap elements, or n_b = n_cur: no progress) -- then with c halved.
- * After a recursion into b, c returns to its initial value.  Once
- * n_cur <= t_fin the subproblem is solved
- * directly: tau = its element of rank k_cur; every element <= tau (in sequence
- * order) is written after the cursor.  More than r_max rounds: status 1.
- *
- * Samples.  The first attempt on the input, and every repeated attempt, uses
- * the skip sampler over the current sequence with stream (seed, tag,
- * segment).  After a recursion into b, the next attempt's sample is drawn
- * while b is formed: each element of b is taken by the per-element rule
- * (orc_hash_taken) with stream tag + 1 and the rate of orc_band_threshold; if
- * that sample exceeds s_max elements it is discarded and the skip sampler is
- * used instead.  The sample is a set: the pivots depend only on its members.
- * Each round is recorded in recs[]. */
-typedef struct {
-    uint32_t n_cur, k_cur;       /* subproblem before the round               */
-    uint32_t s;                  /* sample size                                */
-    uint32_t c_num;              /* pivot spread factor used (c = c_num / 4)   */
-    int64_t lo, hi;              /* pivot sample ranks                         */
-    uint32_t l_idx, r_idx;       /* pivot objects (input positions); 0 if none */
-    uint32_t has_l, has_r;
-    uint32_t na, nb;             /* partition counts                           */
-    uint32_t ok;                 /* 1: recursed into b; 0: round repeated      */
-    uint32_t tag;                /* random stream of this round                */
-} orc_round;
-
-typedef struct {
-    uint32_t s_target;           /* expected sample size                       */
-    uint32_t c_num;              /* initial spread factor numerator (c = /4)   */
-    uint32_t nseg, seg_cap;      /* skip sampler segmentation                  */
-    uint32_t t_fin;              /* solve directly at or below this size       */
-    uint32_t r_max;              /* attempt budget                             */
-    uint64_t band_cap;           /* capacity for b                             */
-    uint64_t seed;
-    uint32_t s_max;              /* largest usable sample                      */
-    uint32_t pad;
-} orc_params;
-
-int orc_replay(const void *keys, int is_f32, uint64_t n, uint64_t k, int largest,
-               const orc_params *prm, uint32_t *out_idx, uint32_t *kth_idx,
-               orc_round *recs, uint32_t *nrecs)
-{
-    if (n == 0 || k == 0 || k > n || n > 0xFFFFFFFFull) return -1;
     orc_order o = {keys, is_f32, largest};
-    uint32_t *cur = (uint32_t *)malloc(n * sizeof(uint32_t));
-    uint32_t *nxt = (uint32_t *)malloc(n * sizeof(uint32_t));
-    uint32_t smax = prm->nseg * prm->seg_cap;
-    uint32_t *spos = (uint32_t *)malloc((smax + 1) * sizeof(uint32_t));
-    uint32_t *samp = (uint32_t *)malloc((smax + 1) * sizeof(uint32_t));
-    if (!cur || !nxt || !spos || !samp) return -2;
-    for (uint64_t i = 0; i < n; ++i) cur[i] = (uint32_t)i;
-    uint64_t n_cur = n, k_cur = k, cursor = 0;
-    uint32_t c_num = prm->c_num, tag = 0, nr = 0;
-    uint32_t *hsamp = (uint32_t *)malloc(((uint64_t)prm->s_max + 1) * sizeof(uint32_t));
-    int64_t hcount = -1;         /* size of the per-element sample of cur; -1: none */
-    int status = 0;
-    if (!hsamp) return -2;
-    for (;;) {
-        if (n_cur <= prm->t_fin) {
-            /* base case: sort the small subproblem, tau = rank k_cur */
-            memcpy(nxt, cur, n_cur * sizeof(uint32_t));
-            qsort_r(nxt, n_cur, sizeof(uint32_t), cmp_idx, &o);
-            uint32_t tau = nxt[k_cur - 1];
-            uint64_t w = 0;
-            for (uint64_t i = 0; i < n_cur; ++i)
-                if (cur[i] == tau || precedes(&o, cur[i], tau))
-                    out_idx[cursor + w++] = cur[i];
-            *kth_idx = tau;
-            if (w != k_cur) status = -3;
-            break;
-        }
-        if (tag >= prm->r_max) { status = 1; break; }
-        int64_t s;
-        if (hcount >= 0) {
-            s = hcount;
-            for (int64_t i = 0; i < s; ++i) samp[i] = hsamp[i];
-        } else {
-            double rho = (double)prm->s_target / (double)n_cur;
-            s = orc_bernoulli_sample(n_cur, rho, prm->seed, tag, prm->nseg,
-                                     prm->seg_cap, spos, smax);
-            if (s < 0) { status = -4; break; }
-            for (int64_t i = 0; i < s; ++i) samp[i] = cur[spos[i]];
-        }
-        hcount = -1;
-        qsort_r(samp, (size_t)s, sizeof(uint32_t), cmp_idx, &o);
-        int64_t lo, hi;
-        orc_pivot_ranks((uint64_t)s, k_cur, n_cur, c_num, &lo, &hi);
-        int has_l = lo >= 0, has_r = hi < s;
-        uint32_t l = has_l ? samp[lo] : 0, r = has_r ? samp[hi] : 0;
-        uint64_t na = 0, nb = 0, hs = 0;
-        uint64_t T = orc_band_threshold(n_cur, (uint64_t)s, lo, hi, prm->s_target);
-        for (uint64_t i = 0; i < n_cur; ++i) {
-            uint32_t e = cur[i];
-            if (has_l && precedes(&o, e, l)) {
-                if (cursor + na < k) out_idx[cursor + na] = e;
-                ++na;
-            } else if (has_r && precedes(&o, r, e)) {
-                /* part c: dropped */
-            } else {
-                if (nb < prm->band_cap) nxt[nb] = e;
-                ++nb;
-                if (orc_hash_taken(prm->seed, tag + 1, e, T)) {
-                    if (hs < prm->s_max) hsamp[hs] = e;
-                    ++hs;
-                }
-            }
-        }
-        int miss = na >= k_cur || na + nb < k_cur;
-        int wide = nb > prm->band_cap || nb == n_cur;
-        int ok = !miss && !wide;
-        if (recs) {
-            orc_round *R = &recs[nr];
-            R->n_cur = (uint32_t)n_cur; R->k_cur = (uint32_t)k_cur; R->s = (uint32_t)s;
-            R->c_num = c_num; R->lo = lo; R->hi = hi;
-            R->l_idx = l; R->r_idx = r; R->has_l = has_l; R->has_r = has_r;
-            R->na = (uint32_t)na; R->nb = (uint32_t)nb; R->ok = ok; R->tag = tag;
-        }
-        ++nr;
-        ++tag;
-        if (miss) {
-            c_num = c_num * 2 > 4096 ? 4096 : c_num * 2;
-            continue;
-        }
-        if (wide) {
-            c_num = c_num / 2;
-            continue;
-        }
-        cursor += na;
-        k_cur -= na;
-        n_cur = nb;
-        uint32_t *t = cur; cur = nxt; nxt = t;
-        c_num = prm->c_num;
-        hcount = hs <= prm->s_max ? (int64_t)hs : -1;
+    uint64_t r = 0;
+    for (uint64_t i = 0; i < n; ++i)
+        if (i != x && precedes(&o, i, x)) ++r;
+    return r;
+}
+
+/* Ranks of m objects xs[0..m) among the objects ys[0..q) (positions into
+ * keys): out[i] = #{j : ys[j] precedes xs[i]}.  O(m q); for sample-sized sets. */
+void orc_rank_among(const void *keys, int is_f32, int largest, const uint32_t *xs, uint64_t m,
+                    const uint32_t *ys, uint64_t q, uint64_t *out)
+{
+    orc_order o = {keys, is_f32, largest};
+    for (uint64_t i = 0; i < m; ++i) {
+        uint64_t r = 0;
+        for (uint64_t j = 0; j < q; ++j)
+            if (ys[j] != xs[i] && precedes(&o, ys[j], xs[i])) ++r;
+        out[i] = r;
     }
-    if (nrecs) *nrecs = nr;
-    free(cur); free(nxt); free(spos); free(samp); free(hsamp);
-    return status;
 }

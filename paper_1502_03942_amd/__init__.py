@@ -20,8 +20,9 @@ TOPK_WRITE_KEYS = 4
 TOPK_TRACE = 8
 TOPK_GRAPH = 16
 STATUS_OK = 0
-STATUS_NO_CONVERGENCE = 1
+STATUS_INTERNAL = 1
 STATUS_BAD_ROW = 2
+ROUND_EXACT = -2
 
 _lib = None
 
@@ -135,7 +136,7 @@ class Context:
 
         u32 keys are passed as torch.uint32 or as torch.int32 holding the bits.
         Returns a dict of device tensors: ``idx`` (int32 holding u32 positions,
-        length k), ``kth_key`` (1 element, dtype of keys), ``kth_idx``,
+        length k, in an unspecified order), ``kth_key`` (1 element, dtype of keys), ``kth_idx``,
         ``status`` and, with ``write_keys``, ``keys``.  ``workspace`` is kept
         in the dict for trace queries.
         """
@@ -265,13 +266,17 @@ class Context:
         return [(self.KERNEL_KINDS[kind[i]], ms[i]) for i in range(min(cnt.value, max_records))]
 
     def trace_rounds(self, res):
-        recs = (RoundRecord * 32)()
+        """Round records of the call that returned ``res`` (topk_trace_rounds)."""
+        cap = 64
+        recs = (RoundRecord * cap)()
         cnt = ctypes.c_uint32()
-        _check(lib().topk_trace_rounds(self._h, _ptr(res["workspace"]), res["n"], recs, 32,
+        _check(lib().topk_trace_rounds(self._h, _ptr(res["workspace"]), res["n"], recs, cap,
                                        ctypes.byref(cnt), _stream(res["workspace"].device)))
-        return [recs[i].as_dict() for i in range(min(cnt.value, 32))]
+        return [recs[i].as_dict() for i in range(min(cnt.value, cap))]
 
     def trace_sample(self, res, tag):
+        """Sampled objects (input positions, unordered) of attempt ``tag`` of the
+        call that returned ``res``, made with ``trace=True`` (topk_trace_sample)."""
         cap = 1 << 16
         buf = (ctypes.c_uint32 * cap)()
         cnt = ctypes.c_uint32()

@@ -1,16 +1,23 @@
-"""Compile the HIP sources of libtopk for gfx950 into paper_1502_03942_amd/libtopk.so."""
+"""Compile the HIP sources of libtopk for gfx950 into paper_1502_03942_amd/libtopk.so.
+
+Every source is compiled to its own object in parallel (each holds its kernels
+and their host launch code, so no relocatable device code is needed), then
+the objects are linked into the shared library.
+"""
 import glob
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtopk.so")
+OBJ = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Wall", "-Wno-unused-function",
     # packed fp32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -23,11 +30,38 @@ def sources():
 
 def build(verbose: bool = False) -> str:
     hipcc = os.path.join(ROCM, "bin", "hipcc")
-    cmd = [hipcc] + HIPCC_FLAGS + ["-I", os.path.join(HERE, "..", "include")] + sources() + [
+    os.makedirs(OBJ, exist_ok=True)
+    inc = ["-I", os.path.join(HERE, "..", "include")]
+    jobs = []
+    for src in sources():
+        obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+        jobs.append((src, obj, [hipcc] + HIPCC_FLAGS + inc + ["-c", src, "-o", obj]))
+
+    def run(job):
+        src, obj, cmd = job
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
+        return src, r.returncode, err
+
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(workers) as ex:
+        results = list(ex.map(run, jobs))
+    failed = False
+    for src, rc, err in results:
+        if err.strip():
+            print(err, file=sys.stderr, flush=True)
+        if rc != 0:
+            print("hipcc failed on %s" % src, file=sys.stderr, flush=True)
+            failed = True
+    if failed:
+        raise subprocess.CalledProcessError(1, "hipcc")
+    link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC"] + [j[1] for j in jobs] + [
         "-o", LIB + ".tmp"]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+        print(" ".join(link), flush=True)
+    subprocess.run(link, check=True)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

@@ -55,7 +55,7 @@ constexpr u32 BT_REG_KEYS = 8192;              // a short row: held in registers
 constexpr int BT_BITS = 10;                     // radix digit
 constexpr u32 BT_BINS = 1u << BT_BITS;
 constexpr int BT_BPT = (int)BT_BINS / BT_THREADS;   // histogram bins per thread in the scan
-constexpr int BT_SEG = 8;                       // sample slots per thread
+constexpr int BT_SEG = 16;                      // sample slots per thread (expected bt_s_target / 256 <= 8)
 constexpr int BT_IPT = 16;                      // keys per thread per sweep step
 constexpr u32 BT_STEP = BT_THREADS * BT_IPT;
 constexpr int BT_NCLS = 34;                     // length classes 0 (empty) .. 33
@@ -837,10 +837,17 @@ __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
                 }
             }
             lds_sync();
-            if (ca >= k || ca + cb < k) {
-                c_num *= 2;                  // the pivots missed rank k: wider
-            } else if (cb > BT_CAP) {
-                c_num = c_num > 1 ? c_num / 2 : 1;   // band too wide for LDS: narrower
+            if (ca >= k || ca + cb < k || cb > BT_CAP) {
+                // The attempt is discarded, and the part below L it wrote to
+                // out[] will be written again by another attempt or by the
+                // exact fallback, possibly by other waves: a barrier that
+                // orders global memory too (not only LDS) puts every earlier
+                // store before the later ones.  The branch is uniform.
+                __syncthreads();
+                if (cb > BT_CAP && !(ca >= k || ca + cb < k))
+                    c_num = c_num > 1 ? c_num / 2 : 1;   // band too wide for LDS: narrower
+                else
+                    c_num *= 2;                  // the pivots missed rank k: wider
             } else {
                 na = ca;
                 nb = cb;

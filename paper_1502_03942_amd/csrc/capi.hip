@@ -189,11 +189,12 @@ int select_common(topk_ctx *c, const K *keys, uint64_t n, uint64_t k, uint32_t f
     P.r_fast = r;
     const int gmax = sweep_max_grid(is_f32, (flags & TOPK_LARGEST) != 0, c->num_cu);
     for (int i = 0; i < 8; ++i) {
-        // round i's expected input, with slack; rounds beyond the plan get the
-        // full grid (they only run after a repeated round)
-        const double ni = (i == 0 || i >= r) ? (double)n : sizes[i] * 1.25 + SW_TILE_BAND;
-        const uint64_t t = (uint64_t)ceil(ni / (i == 0 ? SW_TILE_IN : SW_TILE_BAND)) + 1;
-        P.sweep_grid[i] = (int)(t < (uint64_t)gmax ? t : (uint64_t)gmax);
+        // every sweep gets the full resident grid: a round repeated on a
+        // larger subproblem than planned (a miss re-sweeps its whole input)
+        // keeps every CU, and workgroups without a wave-tile exit at once.
+        // Only the first round's grid is bounded by its wave-tiles.
+        const uint64_t t = (uint64_t)((n + SW_TILE_IN - 1) / SW_TILE_IN) + 1;
+        P.sweep_grid[i] = (i == 0 && t < (uint64_t)gmax) ? (int)t : gmax;
     }
     if (hipSetDevice(c->device) != hipSuccess) return TOPK_E_HIP;
     KernelTimer tm{};
@@ -255,7 +256,7 @@ int topk_set_param(topk_ctx *c, const char *name, int64_t v)
         {"s_target", &c->s_target, 16, 8192},
         {"c_num", &c->c_num, 0, 4096},
         {"t_fin", &c->t_fin, 1, T_FIN_MAX},
-        {"r_max", &c->r_max, 1, R_TRACE},
+        {"r_max", &c->r_max, 1, 32},
         {"r_fast", &c->r_fast, -1, 8},
         {"band_div", &c->band_div, 1, 64},
         {"tail_max", &c->tail_max, 0, (int64_t)1 << 32},

@@ -19,10 +19,11 @@ constexpr int SW_TILE_BAND = SW_DW * 64 * SW_COLS_BAND; // 30720 pairs
 constexpr int SW_STASH = 320;                  // b pairs kept in LDS per wave-tile
 constexpr int SW_SLOTS = 3;                    // wave-tile slots per data wave (pass 2 trails by 2)
 constexpr int S_MAX = PV_THREADS * SEG_CAP;    // largest usable sample (16384)
-constexpr int R_TRACE = 32;                    // attempt records kept
-constexpr int TRACE_STRIDE = NSEG * SEG_CAP;   // sample positions per record
+constexpr int R_TRACE = 34;                    // attempt records kept (r_max <= 32, then the exact round)
+constexpr int TRACE_STRIDE = NSEG * SEG_CAP;   // sampled objects per record
+constexpr int64_t ROUND_EXACT = -2;            // lo = hi of the exact fallback round's record
 
-enum : uint32_t { PH_PIVOT = 0, PH_SWEEP = 1, PH_DONE = 2, PH_ERROR = 3 };
+enum : uint32_t { PH_PIVOT = 0, PH_SWEEP = 1, PH_DONE = 2 };
 
 struct RoundRec {                 // same layout as topk_round_record
     uint32_t n_cur, k_cur, s, c_num;
@@ -52,7 +53,7 @@ struct SelArgs {
     State *st;
     uint32_t band_cap;
     uint32_t *band_ord[2], *band_idx[2];
-    uint32_t *trace_pos;        // [R_TRACE][TRACE_STRIDE] or nullptr
+    uint32_t *trace_pos;        // [R_TRACE][TRACE_STRIDE] sampled objects, or nullptr
     uint64_t *hs_buf;           // [S_MAX] sample drawn while b is formed: ord << 32 | position
     uint32_t *seg_cnt;          // [NSEG] round 1's sample size per segment (k_sample)
     uint32_t s_target, c_num0, t_fin, r_max;

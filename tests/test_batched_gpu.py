@@ -175,3 +175,37 @@ def test_batched_structured_long_rows(dev, largest):
     ctx = tk.Context(0, seed=11)
     res = ctx.select_batched(*to_dev(keys, off, kk, dev), largest=largest)
     check_rows(keys, off, kk, res, largest)
+
+
+def test_batched_fullsize_tuned_as_benched(dev):
+    # the configuration bench.py times: the autotuner's choice on this batch
+    keys, off, kk = synth.lognormal_rows(65536, 4096, 1.0, 64, 1 << 20, 2048, 4)
+    ctx = tk.Context(0, seed=0x5EED)
+    args = to_dev(keys, off, kk, dev)
+    ctx.tune_batched(*args, reps=3)
+    tuned = {c: (ctx.get_param("bt_s_target@%d" % c), ctx.get_param("bt_c_num@%d" % c))
+             for c in range(34) if ctx.get_param("bt_s_target@%d" % c) >= 0}
+    print("tuned:", tuned, "wg/cu", ctx.get_param("bt_wg_per_cu"), flush=True)
+    res = ctx.select_batched(*args, graph=True)
+    res = ctx.select_batched(*args, graph=True, out=res)
+    lens = np.diff(off.astype(np.int64))
+    longest = np.argsort(-lens)[:8].tolist()
+    sample = sorted(set(longest + list(range(0, 65536, 997))))
+    check_rows(keys, off, kk, res, False, rows=sample, full=True)
+    check_rows(keys, off, kk, res, False, full=False)
+
+
+@pytest.mark.parametrize("largest", [False, True])
+def test_batched_general_sweep_retries(dev, largest):
+    # general sweep only, a narrow spread and two attempts: long rows miss,
+    # retry (rewriting the part below L in out[]) and fall back to the exact
+    # select, which rewrites it again
+    rng = np.random.default_rng(60)
+    lens = [9000, 16385, 40000, 100000, 250000, 70000, 12000, 33333]
+    ks = [int(rng.integers(1, min(L, 2048) + 1)) for L in lens]
+    keys, off, kk = ragged(lens * 3, ks * 3, lambda n: synth.normal_f32(n, 61))
+    ctx = tk.Context(0, seed=19)
+    ctx.set_param("bt_fast", 0).set_param("bt_c_num", 4).set_param("bt_attempts", 2)
+    ctx.set_param("bt_s_target", 256)
+    res = ctx.select_batched(*to_dev(keys, off, kk, dev), largest=largest)
+    check_rows(keys, off, kk, res, largest)

@@ -1,17 +1,22 @@
-"""GPU parity at the full workload sizes, in the configuration bench.py times
-(default context parameters).
+"""GPU parity at the full workload sizes.
 
-The oracle's replay of the recursion runs in C in seconds even at 2^28 keys,
-so the whole output array is compared exactly; the O(n) checker confirms it
-against the definition (exactly k distinct positions, all at or below the
-k-th key, counts below/equal adding up, ties by ascending position).
+Each selection runs twice: with the default context parameters, and with the
+parameters the single-instance autotuner picks for it (the configuration
+bench.py times).  Every result is compared with the oracle: the O(n) checker
+confirms it against the definition (exactly k distinct positions, all at or
+below the k-th key, counts below/equal adding up, ties by ascending
+position), and every round is checked definitionally (oracle ranks of the
+pivots give |a| and |b|).  The test-side model of the round policy must
+reproduce the default-parameter trace.
 """
 import numpy as np
 import pytest
 import torch
 
+import model
 import oracle
 import synth
+from roundcheck import check_rounds
 
 pytestmark = pytest.mark.gpu
 
@@ -22,7 +27,7 @@ def to_dev(a, dev):
     return torch.from_numpy(a.view(np.int32) if a.dtype == np.uint32 else a).to(dev)
 
 
-def replay_params(ctx, n):
+def model_params(ctx, n):
     g = ctx.get_param
     t_fin = g("t_fin")
     cap = 0 if n <= t_fin else min(n, n // g("band_div") + 65536)
@@ -30,7 +35,9 @@ def replay_params(ctx, n):
                 t_fin=t_fin, r_max=g("r_max"), band_cap=cap, seed=g("seed"))
 
 
-def compare(ctx, keys_np, keys, k, largest):
+def compare(ctx, keys_np, keys, k, largest, with_model=True):
+    print("fullsize: n=%d k=%d largest=%d s_target=%d c_num=%d" % (
+        keys_np.size, k, largest, ctx.get_param("s_target"), ctx.get_param("c_num")), flush=True)
     res = ctx.select(keys, k, largest=largest)
     torch.cuda.synchronize()
     assert int(res["status"].item()) == 0
@@ -38,15 +45,12 @@ def compare(ctx, keys_np, keys, k, largest):
     kth = int(res["kth_idx"].item())
     kb = int(res["kth_key"].cpu().numpy().view(np.uint32)[0])
     assert oracle.check(keys_np, k, got, kth, kb, largest) == 0
-    rc, rout, rkth, rrecs = oracle.replay(keys_np, k, largest, **replay_params(ctx, keys_np.size))
-    assert rc == 0
-    assert np.array_equal(np.sort(got), np.sort(rout)) and kth == rkth
-    assert ctx.trace_rounds(res) == rrecs
-
-
-@pytest.fixture(scope="module")
-def ctx(dev):
-    return tk.Context(0, seed=0x5EED)
+    recs = ctx.trace_rounds(res)
+    p = model_params(ctx, keys_np.size)
+    check_rounds(keys_np, k, largest, recs, p["band_cap"])
+    if with_model:
+        rc, _, mkth, mrecs = model.replay(keys_np, k, largest, **p)
+        assert rc == 0 and mkth == kth and recs == mrecs
 
 
 @pytest.fixture(scope="module")
@@ -56,14 +60,23 @@ def f32_2p28(dev):
 
 
 @pytest.mark.parametrize("k", [1 << 10, 1 << 20, 1 << 27])
-def test_f32_2p28(ctx, f32_2p28, k):
+def test_f32_2p28(f32_2p28, k):
     keys_np, keys = f32_2p28
-    compare(ctx, keys_np, keys, k, False)
+    compare(tk.Context(0, seed=0x5EED), keys_np, keys, k, False)
 
 
-def test_f32_2p28_largest(ctx, f32_2p28):
+@pytest.mark.parametrize("k", [1 << 10, 1 << 20, 1 << 27])
+def test_f32_2p28_tuned_as_benched(f32_2p28, k):
+    # the bench's configuration: one context per k, autotuned on this selection
     keys_np, keys = f32_2p28
-    compare(ctx, keys_np, keys, 1 << 20, True)
+    ctx = tk.Context(0, seed=0x5EED)
+    ctx.tune(keys, k, reps=3)
+    compare(ctx, keys_np, keys, k, False, with_model=False)
+
+
+def test_f32_2p28_largest(f32_2p28):
+    keys_np, keys = f32_2p28
+    compare(tk.Context(0, seed=0x5EED), keys_np, keys, 1 << 20, True)
 
 
 @pytest.fixture(scope="module")
@@ -73,19 +86,19 @@ def zipf_2p27(dev):
 
 
 @pytest.mark.parametrize("largest", [False, True])
-def test_zipf_2p27(ctx, zipf_2p27, largest):
+def test_zipf_2p27(zipf_2p27, largest):
     keys_np, keys = zipf_2p27
-    compare(ctx, keys_np, keys, 1 << 20, largest)
+    compare(tk.Context(0, seed=0x5EED), keys_np, keys, 1 << 20, largest)
 
 
-def test_all_equal_except_2p27(ctx, dev):
+def test_all_equal_except_2p27(dev):
     keys_np = synth.all_equal_except(1 << 27, 0.01, 1 << 31, 31)
-    compare(ctx, keys_np, to_dev(keys_np, dev), 1 << 20, False)
+    compare(tk.Context(0, seed=0x5EED), keys_np, to_dev(keys_np, dev), 1 << 20, False)
 
 
-def test_u32_2p20_k1000(ctx, dev):
+def test_u32_2p20_k1000(dev):
     keys_np = synth.uniform_u32(1 << 20, 1)
-    res = ctx.select(to_dev(keys_np, dev), 1000)
+    res = tk.Context(0, seed=0x5EED).select(to_dev(keys_np, dev), 1000)
     torch.cuda.synchronize()
     ref = oracle.select_sort(keys_np, 1000)
     got = res["idx"].cpu().numpy().view(np.uint32)

@@ -282,40 +282,6 @@ def test_sampler_full_rate_and_caps():
     assert pos.size == 12
 
 
-def test_hash_sampler_rate_and_independence():
-    # per-element decisions: P(taken) = T / 2^32, independent of the position
-    T = int(0.1 * 2**32)
-    taken = np.array([oracle.hash_taken(77, 3, x, T) for x in range(40000)])
-    p = taken.mean()
-    assert abs(p - 0.1) < 5 * math.sqrt(0.1 * 0.9 / taken.size)
-    # pairs of neighbours are uncorrelated
-    both = np.mean(taken[:-1] & taken[1:])
-    assert abs(both - 0.01) < 5 * math.sqrt(0.01 / taken.size)
-    # T = 0 takes nothing, T = 2^32 takes everything; another tag is another stream
-    assert not any(oracle.hash_taken(77, 3, x, 0) for x in range(100))
-    assert all(oracle.hash_taken(77, 3, x, 2**32) for x in range(100))
-    other = np.array([oracle.hash_taken(77, 4, x, T) for x in range(40000)])
-    assert 0 < np.sum(taken != other) and abs(np.mean(taken & other) - 0.01) < 0.003
-
-
-def test_hash_sampler_matches_philox_word():
-    # the decision is word 0 of Philox4x32-10 at counter (x, 0, tag, 1), key = seed
-    seed = 0x1234_5678_9ABC_DEF0
-    for x, tag in ((0, 0), (5, 1), (2**31 + 7, 9)):
-        w = int(oracle.philox4x32_10([x, 0, tag, 1], [seed & 0xFFFFFFFF, seed >> 32])[0])
-        assert oracle.hash_taken(seed, tag, x, w + 1) and not oracle.hash_taken(seed, tag, x, w)
-
-
-def test_band_threshold_hand_worked():
-    # pivots cover ranks [bot, top): expected b = n (top - bot) / s, rho = s_target / that
-    # n = 2^28, s = 4096, lo = 1919, hi = 2177: b ~ 2^28 * 259 / 4096 = 16973824
-    assert oracle.band_threshold(2**28, 4096, 1919, 2177, 4096) == (4096 << 32) // 16973824
-    # no lower pivot (lo < 0): bot = 0; hi = 6 -> top = 7: b ~ 2^28 * 7 / 4096 = 458752
-    assert oracle.band_threshold(2**28, 4096, -5, 6, 4096) == (4096 << 32) // 458752
-    # no pivots at all: b ~ n
-    assert oracle.band_threshold(1000, 10, -3, 12, 4096) == (4096 << 32) // 1000
-
-
 # ---------------------------------------------------------------- pivots ----
 
 def test_pivot_ranks_hand_worked():
@@ -350,100 +316,53 @@ def test_pivot_bracketing_rate():
     assert miss05 > 200
 
 
-# ------------------------------------------------------------------ replay --
+# ------------------------------------------------------- composite sort ---
 
-REPLAY_CASES = [
-    dict(s_target=256, c_num=16, nseg=64, seg_cap=16, t_fin=512, r_max=32),
-    dict(s_target=64, c_num=16, nseg=16, seg_cap=16, t_fin=64, r_max=64),
-    dict(s_target=1024, c_num=8, nseg=1024, seg_cap=4, t_fin=2048, r_max=32),
-    dict(s_target=128, c_num=0, nseg=32, seg_cap=16, t_fin=100, r_max=200),  # many misses
-]
-
-
-def _replay_equals_plain(keys, k, largest, prm, seed, band_cap=None):
-    n = keys.size
-    rc, out, kth, recs = oracle.replay(keys, k, largest, seed=seed,
-                                       band_cap=band_cap or n, **prm)
-    assert rc == 0, (rc, recs[-3:])
-    ref = oracle.select_sort(keys, k, largest)
-    assert np.array_equal(np.sort(out), np.sort(ref))
-    assert kth == int(ref[-1])
-    # every round that recursed bracketed rank k_cur and shrank the problem
-    for r in recs:
-        if r["ok"]:
-            assert r["na"] < r["k_cur"] <= r["na"] + r["nb"] and r["nb"] < r["n_cur"]
-    return recs
-
-
-@pytest.mark.parametrize("case", range(len(REPLAY_CASES)))
+@pytest.mark.parametrize("gen", ["u32", "alpha3", "specials", "grid"])
 @pytest.mark.parametrize("largest", [False, True])
-def test_replay_equals_plain_oracle(case, largest):
-    prm = REPLAY_CASES[case]
-    rng = np.random.default_rng(case)
-    gens = [lambda n, s: synth.uniform_u32(n, s),
-            lambda n, s: synth.small_alphabet_u32(n, 3, s),
-            lambda n, s: synth.specials_f32(n, s),
-            lambda n, s: synth.uniform_f32_grid(n, s),
-            lambda n, s: synth.zipf_u32(n, 1.2, 2**16, s),
-            lambda n, s: synth.all_equal_except(n, 0.01, 2**31, s)]
-    for gi, g in enumerate(gens):
-        n = int(rng.integers(1, 60000))
-        keys = g(n, 100 * case + gi)
-        for k in {1, n, max(1, n // 2), int(rng.integers(1, n + 1))}:
-            _replay_equals_plain(keys, k, largest, prm, seed=gi * 7 + case)
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_composite_sort_equals_plain_oracle(gen, largest, threads):
+    # the timed form (composite keys, chunked over threads) is the plain
+    # comparator sort: same first k, in the same order
+    n = 20011
+    keys = {"u32": synth.uniform_u32(n, 8), "alpha3": synth.small_alphabet_u32(n, 3, 9),
+            "specials": synth.specials_f32(n, 10), "grid": synth.uniform_f32_grid(n, 11)}[gen]
+    for k in (1, 2, 777, n // 2, n):
+        a = oracle.select_composite(keys, k, largest, threads)
+        b = oracle.select_sort(keys, k, largest)
+        assert np.array_equal(a, b), (gen, k)
 
 
-def test_replay_rounds_and_output_layout():
-    # a-elements of each round are written in sequence order, so the first
-    # round's segment is ascending in position
-    keys = synth.uniform_u32(200000, 4)
-    k = 100000
-    prm = dict(s_target=512, c_num=16, nseg=128, seg_cap=16, t_fin=256, r_max=32)
-    rc, out, kth, recs = oracle.replay(keys, k, seed=1, band_cap=200000, **prm)
-    assert rc == 0 and len(recs) >= 2
-    na1 = recs[0]["na"]
-    assert recs[0]["ok"] and np.all(np.diff(out[:na1].astype(np.int64)) > 0)
+# ------------------------------------------------------------------ ranks ---
+
+@pytest.mark.parametrize("gen", ["u32", "alpha3", "specials"])
+@pytest.mark.parametrize("largest", [False, True])
+def test_rank_is_position_in_sorted_order(gen, largest):
+    # rank(x) = #{objects before x}: the position of x in the full sort, and
+    # the brute-force selection of k holds exactly the objects of rank < k
+    n = 700
+    keys = {"u32": synth.uniform_u32(n, 3), "alpha3": synth.small_alphabet_u32(n, 3, 4),
+            "specials": synth.specials_f32(n, 5)}[gen]
+    perm = oracle.select_sort(keys, n, largest)
+    for pos in (0, 1, 17, 350, n - 2, n - 1):
+        assert oracle.rank(keys, int(perm[pos]), largest) == pos
+    sel, kth = oracle.select_brute(keys, 123, largest)
+    ranks = np.array([oracle.rank(keys, int(x), largest) for x in range(n)])
+    assert np.array_equal(np.flatnonzero(ranks < 123), np.sort(sel))
+    assert ranks[kth] == 122
 
 
-def test_replay_wide_band_halves_spread():
-    # s_target = 16 at the median: Delta >= s/2 with c = 4, so b is the whole
-    # subproblem; halving c restores progress
-    keys = synth.small_alphabet_u32(20000, 5, 4)
-    rc, out, kth, recs = oracle.replay(keys, 10000, s_target=16, c_num=16, nseg=1024,
-                                       seg_cap=16, t_fin=512, r_max=32, band_cap=20000, seed=5)
-    assert rc == 0
-    assert not recs[0]["ok"] and recs[0]["nb"] == recs[0]["n_cur"]
-    assert recs[1]["c_num"] == 8
-    ref = oracle.select_sort(keys, 10000)
-    assert np.array_equal(np.sort(out), np.sort(ref)) and kth == ref[-1]
-
-
-def test_replay_miss_doubles_spread():
-    keys = synth.uniform_u32(300000, 9)
-    rc, out, kth, recs = oracle.replay(keys, 77, s_target=256, c_num=0, nseg=1024,
-                                       seg_cap=16, t_fin=512, r_max=32, band_cap=300000, seed=3)
-    assert rc == 0
-    for a, b in zip(recs, recs[1:]):
-        if not a["ok"] and (a["na"] >= a["k_cur"] or a["na"] + a["nb"] < a["k_cur"]):
-            assert b["c_num"] == min(2 * a["c_num"], 4096)
-
-
-def test_replay_band_cap_overflow_and_budget():
-    keys = synth.uniform_u32(50000, 5)
-    prm = dict(s_target=64, c_num=16, nseg=16, seg_cap=16, t_fin=64, r_max=6)
-    rc, out, kth, recs = oracle.replay(keys, 25000, seed=1, band_cap=10, **prm)
-    assert rc == 1 and len(recs) == 6 and not any(r["ok"] for r in recs)
-
-
-def test_replay_direct_finish_when_small():
-    keys = synth.uniform_u32(100, 6)
-    rc, out, kth, recs = oracle.replay(keys, 40, s_target=64, c_num=16, nseg=4, seg_cap=64,
-                                       t_fin=100, r_max=4, band_cap=100, seed=3)
-    assert rc == 0 and recs == []
-    ref = oracle.select_sort(keys, 40)
-    assert kth == ref[-1]
-    # the direct finish writes the selected elements in position order
-    assert np.array_equal(out, np.sort(ref))
+def test_rank_among_counts_subset():
+    keys = synth.small_alphabet_u32(500, 4, 7)
+    xs = np.array([3, 99, 250, 499], np.uint32)
+    ys = np.arange(0, 500, 3, dtype=np.uint32)
+    got = oracle.rank_among(keys, xs, ys)
+    for x, g in zip(xs, got):
+        want = sum(1 for y in ys if y != x and oracle.precedes(keys, int(y), int(x)))
+        assert g == want
+    # among all objects it is the rank
+    assert list(oracle.rank_among(keys, xs, np.arange(500, dtype=np.uint32))) == \
+        [oracle.rank(keys, int(x)) for x in xs]
 
 
 # ---------------------------------------------------------- rows / scatter --
