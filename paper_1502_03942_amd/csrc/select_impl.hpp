@@ -555,6 +555,7 @@ __device__ __noinline__ void exact_pivot(const SelArgs &a, State *st, Smem &sm)
         }
         __syncthreads();
         const u32 m = *gcount;
+        __syncthreads();                    // radix_select clears rhist (and the count)
         u64 v[SEG_CAP];
         int c = 0;
 #pragma unroll
