@@ -132,7 +132,8 @@ int topk_select_f32(topk_ctx *ctx, const float *keys, uint64_t n, uint64_t k,
 /* One recorded round of the last select call that used `workspace`
  * (§2 Algorithm: sample, pivots l = S[lo] and r = S[hi], counts of a and b).
  * The exact fallback round (after r_max attempts) has s = 0 and
- * lo = hi = TOPK_ROUND_EXACT: both pivots are the object of rank k_cur. */
+ * lo = hi = TOPK_ROUND_EXACT: both pivots are the object of rank k_cur (a
+ * sampled round always has hi >= 0; its lo < 0 means "no lower pivot"). */
 #define TOPK_ROUND_EXACT (-2)
 typedef struct topk_round_record {
     uint32_t n_cur, k_cur;   /* subproblem entering the round                    */

@@ -41,8 +41,8 @@ def check_rounds(keys, k, largest, recs, band_cap, sample_of=None):
     oks = 0
     for r in recs:
         assert (r["n_cur"], r["k_cur"]) == (n_cur, k_cur), r
-        if r["lo"] == ROUND_EXACT:
-            assert r["hi"] == ROUND_EXACT and r["s"] == 0 and r["has_l"] and r["has_r"], r
+        if r["hi"] == ROUND_EXACT:      # a sampled round has hi >= 0
+            assert r["lo"] == ROUND_EXACT and r["s"] == 0 and r["has_l"] and r["has_r"], r
             assert r["l_idx"] == r["r_idx"], r
             rl = rr = oracle.rank(keys, r["l_idx"], largest)
             assert rl == A + k_cur - 1, (r, A)

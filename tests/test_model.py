@@ -164,3 +164,24 @@ def test_replay_direct_finish_when_small():
     assert np.array_equal(out, np.sort(ref))
 
 
+
+
+@pytest.mark.parametrize("largest", [False, True])
+def test_model_traces_pass_the_definitional_round_check(largest):
+    # the checker the GPU tests apply to device traces accepts the model's
+    # traces (misses, too-wide rounds and the exact round included) ...
+    from roundcheck import check_rounds
+    keys = synth.zipf_u32(300000, 1.2, 2**16, 3)
+    for k, c_num, r_max, cap in ((1, 8, 5, 300000), (1000, 0, 5, 300000),
+                                 (150000, 8, 5, 300000), (150000, 16, 3, 10)):
+        rc, out, kth, recs = model.replay(keys, k, largest, seed=1, band_cap=cap, s_target=256,
+                                          c_num=c_num, nseg=64, seg_cap=16, t_fin=512, r_max=r_max)
+        assert rc == 0
+        check_rounds(keys, k, largest, recs, cap)
+    # ... and rejects a trace with a miscounted |a|
+    rc, out, kth, recs = model.replay(keys, 1000, largest, seed=1, band_cap=300000, s_target=256,
+                                      c_num=8, nseg=64, seg_cap=16, t_fin=512, r_max=5)
+    bad = [dict(r) for r in recs]
+    bad[0]["na"] += 1
+    with pytest.raises(AssertionError):
+        check_rounds(keys, 1000, largest, bad, 300000)

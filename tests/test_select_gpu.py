@@ -88,7 +88,7 @@ def run_and_compare(ctx, keys_np, k, largest, dev, offset=0, trace=True, exact_t
             assert g == r, (g, r)
             if not g["ok"] and g["n_cur"] < n:
                 break
-    if trace and mrecs and mrecs[0]["lo"] != ROUND_EXACT:
+    if trace and mrecs and mrecs[0]["hi"] != ROUND_EXACT:
         # round 1's sampled objects follow the skip sampler's law exactly
         p = model_params(ctx, n)
         pos = np.sort(np.array(ctx.trace_sample(res, 0), np.uint32))
@@ -151,7 +151,7 @@ def test_exact_fallback_after_band_overflow(dev, largest):
     c.set_param("c_num", 4096).set_param("r_max", 3).set_param("t_fin", 1024)
     keys = synth.uniform_u32(1 << 20, 10)
     recs = run_and_compare(c, keys, 1 << 19, largest, dev)
-    assert [r["lo"] for r in recs][-1] == ROUND_EXACT and not any(r["ok"] for r in recs[:3])
+    assert [r["hi"] for r in recs][-1] == ROUND_EXACT and not any(r["ok"] for r in recs[:3])
 
 
 @pytest.mark.parametrize("dist", ["u32", "zipf", "f32_special"])
@@ -163,7 +163,7 @@ def test_exact_fallback_on_a_band(dev, dist):
     keys = DISTS[dist](1 << 20, 41)
     for k, largest in ((1, False), (5000, True), (1 << 19, False), (1 << 20, True)):
         recs = run_and_compare(c, keys, k, largest, dev, exact_trace=False)
-        assert recs[-1]["lo"] == ROUND_EXACT or recs[-1]["n_cur"] <= 64
+        assert recs[-1]["hi"] == ROUND_EXACT or recs[-1]["n_cur"] <= 64
 
 
 def test_exact_fallback_first_round_multi_workgroup(dev):
@@ -174,7 +174,7 @@ def test_exact_fallback_first_round_multi_workgroup(dev):
     exact = 0
     for k in (1, 777, 1 << 21, (1 << 22) - 3):
         recs = run_and_compare(c, keys, k, False, dev)
-        exact += sum(1 for r in recs if r["lo"] == ROUND_EXACT)
+        exact += sum(1 for r in recs if r["hi"] == ROUND_EXACT)
     assert exact > 0
 
 
@@ -198,7 +198,7 @@ def test_tiny_t_fin_finishes_exactly(dev):
     keys = synth.small_alphabet_u32(20000, 5, 4)
     for k in (1, 10000, 20000):
         recs = run_and_compare(c, keys, k, False, dev, exact_trace=False)
-        assert recs[-1]["lo"] == ROUND_EXACT
+        assert recs[-1]["hi"] == ROUND_EXACT
 
 
 def test_deterministic_repeat(ctx, dev):
