@@ -161,9 +161,15 @@ def test_exact_fallback_on_a_band(dev, dist):
     c = tk.Context(0, seed=8).set_param("s_target", 64).set_param("t_fin", 64)
     c.set_param("r_max", 2).set_param("r_fast", 2)
     keys = DISTS[dist](1 << 20, 41)
+    exact = 0
     for k, largest in ((1, False), (5000, True), (1 << 19, False), (1 << 20, True)):
         recs = run_and_compare(c, keys, k, largest, dev, exact_trace=False)
-        assert recs[-1]["hi"] == ROUND_EXACT or recs[-1]["n_cur"] <= 64
+        last = recs[-1]
+        # the call ends in the exact round or in a sampled round that leaves
+        # at most t_fin objects for the finisher
+        assert last["hi"] == ROUND_EXACT or (last["ok"] and last["nb"] <= 64)
+        exact += last["hi"] == ROUND_EXACT
+    assert exact > 0
 
 
 def test_exact_fallback_first_round_multi_workgroup(dev):
