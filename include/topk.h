@@ -237,6 +237,27 @@ int topk_select_batched_f32(topk_ctx *ctx, const float *keys, const uint64_t *ro
                             uint32_t *kth_idx, uint32_t *status, void *workspace,
                             size_t ws_bytes, hipStream_t stream);
 
+/* topk_select_batched_f32_noalloc: topk_select_batched_f32 for callers that
+ * cannot allocate device memory or pass a workspace (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation).  Same
+ * arguments, results and kernels, without workspace and ws_bytes: the
+ * workspace is a file-scope device array of the library (4 MiB + 768 bytes on
+ * every device the library runs on, held until the process ends), enough for
+ * rows <= 1,048,576.  No call allocates anything (no hipMalloc, no hipFree,
+ * no allocating library routine); the library looks the array's device
+ * address up once per device in topk_create.  Every call on a device shares
+ * that array, and the launches clear what must start at zero: calls that
+ * overlap on one device (different streams, or different host threads
+ * without ordering) race and give undefined results.
+ * flags: TOPK_LARGEST only (TOPK_GRAPH is rejected: the library would have
+ * to create a stream and instantiate a graph; capture the call instead).
+ * Returns TOPK_OK, TOPK_E_INVALID (as topk_select_batched_f32, or an unknown
+ * flag), TOPK_E_WORKSPACE (rows > 1,048,576) or TOPK_E_HIP. */
+int topk_select_batched_f32_noalloc(topk_ctx *ctx, const float *keys, const uint64_t *row_off,
+                                    uint32_t rows, const uint32_t *k, const uint64_t *out_off,
+                                    uint32_t flags, uint32_t *out_idx, float *kth_key,
+                                    uint32_t *kth_idx, uint32_t *status, hipStream_t stream);
+
 /* topk_tune_batched_f32: the autotuner of the batched form.  Same arguments
  * as topk_select_batched_f32 (TOPK_GRAPH ignored; the outputs are
  * overwritten with valid results).  For every length class of the batch whose

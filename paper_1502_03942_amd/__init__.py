@@ -73,6 +73,7 @@ def lib():
     L.topk_batched_workspace_bytes.argtypes = [vp, u32, u32]
     L.topk_batched_workspace_bytes.restype = sz
     L.topk_select_batched_f32.argtypes = [vp, vp, vp, u32, vp, vp, u32, vp, vp, vp, vp, vp, sz, vp]
+    L.topk_select_batched_f32_noalloc.argtypes = [vp, vp, vp, u32, vp, vp, u32, vp, vp, vp, vp, vp]
     L.topk_tune_batched_f32.argtypes = [vp, vp, vp, u32, vp, vp, u32, vp, vp, vp, vp, vp, sz, u32, vp]
     L.topk_save_tuning.argtypes = [vp, ctypes.c_char_p]
     L.topk_tune_f32.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_uint64, u32, vp, vp, vp, vp, sz,
@@ -234,6 +235,18 @@ class Context:
             self._h, _ptr(keys), _ptr(row_off), R, _ptr(k), _ptr(out["out_off"]), flags,
             _ptr(out["idx"]), _ptr(out["kth_key"]), _ptr(out["kth_idx"]), _ptr(out["status"]),
             _ptr(ws), ws.numel(), _stream(keys.device)))
+        return out
+
+    def select_batched_noalloc(self, keys, row_off, k, out_off, out, largest=False):
+        """topk_select_batched_f32_noalloc: the batched selection with the
+        library's static scratch instead of a workspace.  ``out`` is a dict of
+        caller-allocated outputs (``idx``, ``kth_key``, ``kth_idx``,
+        ``status``); nothing is allocated here."""
+        R = row_off.numel() - 1
+        _check(lib().topk_select_batched_f32_noalloc(
+            self._h, _ptr(keys), _ptr(row_off), R, _ptr(k), _ptr(out_off),
+            TOPK_LARGEST if largest else 0, _ptr(out["idx"]), _ptr(out["kth_key"]),
+            _ptr(out["kth_idx"]), _ptr(out["status"]), _stream(keys.device)))
         return out
 
     def tune_batched(self, keys, row_off, k, out_off=None, largest=False, reps=3, out=None):

@@ -40,6 +40,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -985,6 +986,23 @@ BtLayout bt_layout(uint32_t rows)
     return L;
 }
 
+// ---- Scratch of topk_select_batched_f32_noalloc ----------------------------
+// The same layout as a caller's workspace, for at most BT_NOALLOC_MAX_ROWS
+// rows, in a file-scope device array that every call on a device shares.
+constexpr uint32_t BT_NOALLOC_MAX_ROWS = 1u << 20;
+constexpr size_t BT_NOALLOC_BYTES =
+    3 * BT_ALIGN + (((size_t)BT_NOALLOC_MAX_ROWS * sizeof(uint32_t) + BT_ALIGN - 1) / BT_ALIGN) * BT_ALIGN;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[BT_NOALLOC_BYTES];
+
+namespace {
+
+constexpr int BT_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[BT_MAX_DEVICES];    // device address of `scratch` on each device
+
 hipError_t bt_enqueue(const BtArgs &a, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(k_bt_init, dim3(1), dim3(64), 0, s, a);
@@ -999,6 +1017,28 @@ hipError_t bt_enqueue(const BtArgs &a, int grid, hipStream_t s)
 }
 
 }  // namespace
+
+// Look up the device address of `scratch` on `device` (once per device; the
+// host-side name of the array is not a device address).  Called by
+// topk_create; makes `device` current while it runs and restores the caller's.
+int topk_bt_scratch_setup(int device)
+{
+    static_assert(BT_NOALLOC_BYTES >= 3 * BT_ALIGN + BT_NOALLOC_MAX_ROWS * sizeof(uint32_t),
+                  "scratch holds the workspace layout of the largest batch");
+    if (device < 0 || device >= BT_MAX_DEVICES) return TOPK_E_INVALID;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return TOPK_OK;
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) return TOPK_E_HIP;
+    if (hipSetDevice(device) != hipSuccess) return TOPK_E_HIP;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess || !ptr) return TOPK_E_HIP;
+    if (bt_layout(BT_NOALLOC_MAX_ROWS).total > BT_NOALLOC_BYTES) return TOPK_E_HIP;
+    g_scratch_ptr[device] = ptr;
+    return TOPK_OK;
+}
 
 extern "C" size_t topk_batched_workspace_bytes(const topk_ctx *ctx, uint32_t rows, uint32_t flags)
 {
@@ -1192,4 +1232,28 @@ extern "C" int topk_tune_batched_f32(topk_ctx *c, const float *keys, const uint6
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
+}
+
+extern "C" int topk_select_batched_f32_noalloc(topk_ctx *c, const float *keys,
+                                               const uint64_t *row_off, uint32_t rows,
+                                               const uint32_t *k, const uint64_t *out_off,
+                                               uint32_t flags, uint32_t *out_idx, float *kth_key,
+                                               uint32_t *kth_idx, uint32_t *status,
+                                               hipStream_t stream)
+{
+    if (!c) return TOPK_E_INVALID;
+    if (flags & ~(uint32_t)TOPK_LARGEST) return TOPK_E_INVALID;   // no graph capture here
+    if (rows > BT_NOALLOC_MAX_ROWS) return TOPK_E_WORKSPACE;
+    if (c->device < 0 || c->device >= BT_MAX_DEVICES) return TOPK_E_INVALID;
+    void *ptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        ptr = g_scratch_ptr[c->device];
+    }
+    if (!ptr) return TOPK_E_HIP;                // topk_create sets it up
+    BtArgs a;
+    const int rc = bt_args(c, keys, row_off, rows, k, out_off, flags, out_idx, kth_key, kth_idx,
+                           status, ptr, BT_NOALLOC_BYTES, a);
+    if (rc != TOPK_OK) return rc;
+    return bt_run(c, a, false, stream);
 }

@@ -230,6 +230,8 @@ int topk_create(topk_ctx **out, int hip_device, uint64_t seed)
     int ncu = 0;
     int rc = check_device(hip_device, &ncu);
     if (rc != TOPK_OK) return rc;
+    rc = topk_bt_scratch_setup(hip_device);
+    if (rc != TOPK_OK) return rc;
     topk_ctx *c = new (std::nothrow) topk_ctx;
     if (!c) return TOPK_E_INVALID;
     c->device = hip_device;

@@ -29,3 +29,7 @@ struct topk_ctx {
     hipStream_t capture_stream = nullptr;
     std::map<std::vector<uint64_t>, hipGraphExec_t> graphs;
 };
+
+// Device address of the scratch array of topk_select_batched_f32_noalloc on
+// `device`, looked up once per device (batched.hip).
+int topk_bt_scratch_setup(int device);
