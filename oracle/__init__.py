@@ -25,7 +25,8 @@ def lib():
     global _lib
     if _lib is None:
         path = os.path.join(_HERE, "liboracle.so")
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+        if not os.path.exists(path) or \
+                os.path.getmtime(path) < max(os.path.getmtime(f) for f in _build.SOURCES):
             _build.build()
         L = ctypes.CDLL(path)
         vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
@@ -40,6 +41,12 @@ def lib():
         L.orc_bernoulli_sample.restype = ctypes.c_int64
         L.orc_pivot_ranks.argtypes = [u64, u64, u64, u32, vp, vp]
         L.orc_pivot_ranks.restype = None
+        L.orc_take.argtypes = [u64, u32, u64, u64]
+        L.orc_sample_counts.argtypes = [vp, u64, u32, u64, u32, u64, vp, vp]
+        L.orc_exact_counts.argtypes = [vp, u64, u32, vp]
+        L.orc_sum_by_key.argtypes = [vp, vp, u64, u32, vp]
+        L.orc_weighted_sample.argtypes = [vp, u32, u64, u64, u32, vp]
+        L.orc_weighted_sample.restype = ctypes.c_int64
         L.orc_rank.argtypes = [vp, i32, u64, i32, u32]
         L.orc_rank.restype = u64
         L.orc_rank_among.argtypes = [vp, i32, i32, vp, u64, vp, u64, vp]
@@ -187,3 +194,6 @@ def scatter_rows(grad_out, indices, n_cols):
         for m in range(grad_out.shape[1]):
             g[b, indices[b, m]] = grad_out[b, m]
     return g
+
+
+from . import freq  # noqa: E402,F401  (top-k most frequent objects and sum aggregation)

@@ -9,12 +9,13 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "topk_oracle.c")
+SOURCES = [SRC, os.path.join(HERE, "freq_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
-           "-o", LIB + ".tmp", SRC, "-lm", "-lpthread"]
+           "-o", LIB + ".tmp"] + SOURCES + ["-lm", "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
