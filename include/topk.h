@@ -62,6 +62,9 @@ extern "C" {
 #define TOPK_STATUS_INTERNAL 1u        /* an internal consistency check failed (a
                                           library defect); outputs invalid          */
 #define TOPK_STATUS_BAD_ROW 2u         /* batched: some row had k = 0 or k > len      */
+#define TOPK_STATUS_BAD_KEY 4u         /* frequent / sum: a key >= U was skipped      */
+#define TOPK_STATUS_SUM_RANGE 8u       /* sum: the sum of all values is >= 2^63, so
+                                          the weighted sample is empty              */
 
 typedef struct topk_ctx topk_ctx;
 
@@ -315,6 +318,87 @@ int topk_rows_fwd_f32(topk_ctx *ctx, const float *scores, uint32_t B, uint32_t N
  * 2^31 - 1 workgroups) or TOPK_E_HIP. */
 int topk_scatter_bwd_f32(const float *grad_out, const int64_t *indices, uint32_t B,
                          uint32_t N, uint32_t k, float *grad_in, hipStream_t stream);
+
+/* ---- Top-k most frequent objects (§7) and top-k sum aggregation (§8) ----
+ *
+ * Objects are integers in [0, U).  One device stands in for the paper's PEs,
+ * so the distributed hash table of §7.1 is a count table over [0, U) in the
+ * workspace, fed by per-workgroup LDS hash tables (local aggregation).
+ * "Most frequent" follows the unique order of §2 with the count as the
+ * value: larger counts first, ties by ascending object.
+ *
+ * topk_frequent_u32: the k most frequent objects of keys[0..n).
+ *   keys      [n]  objects, each < U (others are skipped and flagged in
+ *                  status); 16-byte aligned; 1 <= n < 2^32
+ *   U              universe size, 1 <= U <= 2^31
+ *   k              1 <= k <= min(U, 4096)
+ *   kstar     0: Algorithm PAC (§7.1): Bernoulli sample, count the sampled
+ *                  objects, select the k most frequently sampled;
+ *             else Algorithm EC (§7.2), k <= kstar <= min(U, 4096): select
+ *                  the kstar most frequently sampled, count those exactly
+ *                  over the whole input, return the k most frequent of them
+ *   T              sampling rate rho = T / 2^32, 1 <= T <= 2^32 (2^32:
+ *                  every element); element i is sampled iff word i % 4 of
+ *                  Philox4x32-10 at counter (i / 4, 0, 0, 2), key = the
+ *                  context seed, is below T (topk_sample_threshold makes T
+ *                  from a sample size)
+ *   out_ids   [k]  the objects, most frequent first (ties: ascending object)
+ *   out_counts[k]  PAC: their sample counts (the estimate of a count is
+ *                  count * 2^32 / T); EC: their exact counts
+ *   sample_counts [U]  NULL, or receives every object's sample count
+ *   n_sampled [1]  NULL, or receives the sample size
+ *   status    [1]  TOPK_STATUS_OK or TOPK_STATUS_BAD_KEY
+ *   workspace      >= topk_frequent_workspace_bytes(ctx, U), 256-byte aligned
+ * Asynchronous on `stream`.  Returns TOPK_OK, TOPK_E_INVALID,
+ * TOPK_E_WORKSPACE or TOPK_E_HIP. */
+size_t topk_frequent_workspace_bytes(const topk_ctx *ctx, uint32_t U);
+int topk_frequent_u32(topk_ctx *ctx, const uint32_t *keys, uint64_t n, uint32_t U, uint32_t k,
+                      uint32_t kstar, uint64_t T, uint32_t *out_ids, uint32_t *out_counts,
+                      uint32_t *sample_counts, uint64_t *n_sampled, uint32_t *status,
+                      void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* topk_sum_top_u32: the k keys with the largest sums of values (§8).
+ *   keys, values [n]  pairs (key < U, value >= 0), each array 16-byte aligned;
+ *                  1 <= n < 2^32; the sum of all values must be < 2^63
+ *   s              desired sample size, 1 <= s < 2^31.  The input is first
+ *                  aggregated by key (sums[x]); with v_avg = m / s (m the
+ *                  sum of all values) key x then yields floor(sums[x] /
+ *                  v_avg) samples plus one with probability sums[x] / v_avg
+ *                  minus that (word 0 of Philox4x32-10 at counter (x, 0, 0,
+ *                  3), key = the context seed, below floor(r 2^32 / m), r =
+ *                  sums[x] s mod m)
+ *   kstar     0: PAC: the k keys with the most samples; out_vals = their
+ *                  sample counts (estimate: count * m / s);
+ *             else, k <= kstar <= min(U, 4096): the kstar keys with the most
+ *                  samples, then the k largest of them by exact sum
+ *                  (out_vals = exact sums)
+ *   out_ids [k], out_vals [k]  keys (largest first, ties: ascending key), values
+ *   sums [U], samples [U]      NULL, or receive the sums by key / the samples
+ *   status    [1]  TOPK_STATUS_OK, TOPK_STATUS_BAD_KEY, TOPK_STATUS_SUM_RANGE
+ *   workspace      >= topk_sum_workspace_bytes(ctx, U), 256-byte aligned
+ * Asynchronous on `stream`.  Returns TOPK_OK, TOPK_E_INVALID,
+ * TOPK_E_WORKSPACE or TOPK_E_HIP. */
+size_t topk_sum_workspace_bytes(const topk_ctx *ctx, uint32_t U);
+int topk_sum_top_u32(topk_ctx *ctx, const uint32_t *keys, const uint32_t *values, uint64_t n,
+                     uint32_t U, uint32_t k, uint32_t kstar, uint64_t s, uint32_t *out_ids,
+                     uint64_t *out_vals, uint64_t *sums, uint32_t *samples, uint32_t *status,
+                     void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* Sample sizes (host): the expected sample size for an (eps, delta)
+ * approximation of §7 and §8 (0 < eps, 0 < delta < 1):
+ *   TOPK_SAMPLE_PAC  4/eps^2 max(3/k ln(4n/delta), 2 ln(2k/delta))  (§7.1, equation
+ *                    "sampleSize")
+ *   TOPK_SAMPLE_EC   2/(eps^2 kstar) ln(n/delta)                    (§7.2, Lemma "topkec")
+ *   TOPK_SAMPLE_SUM  (1/eps) sqrt(2 ln(2n/delta))                   (§8, proof of Theorem
+ *                    "sumpac", one PE)
+ * Returns -1 for invalid arguments.  topk_sample_threshold turns a sample
+ * size into T = min(2^32, ceil(size 2^32 / n)) (at least 1). */
+#define TOPK_SAMPLE_PAC 0
+#define TOPK_SAMPLE_EC 1
+#define TOPK_SAMPLE_SUM 2
+double topk_sample_size(int method, uint64_t n, uint32_t k, uint32_t kstar, double eps,
+                        double delta);
+uint64_t topk_sample_threshold(uint64_t n, double sample_size);
 
 const char *topk_strerror(int code);
 

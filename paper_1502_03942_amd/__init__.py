@@ -82,6 +82,17 @@ def lib():
     L.topk_load_tuning.argtypes = [vp, ctypes.c_char_p]
     L.topk_rows_fwd_f32.argtypes = [vp, vp, u32, u32, u32, u32, vp, vp, vp]
     L.topk_scatter_bwd_f32.argtypes = [vp, vp, u32, u32, u32, vp, vp]
+    L.topk_frequent_workspace_bytes.argtypes = [vp, u32]
+    L.topk_frequent_workspace_bytes.restype = sz
+    L.topk_frequent_u32.argtypes = [vp, vp, u64, u32, u32, u32, u64, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.topk_sum_workspace_bytes.argtypes = [vp, u32]
+    L.topk_sum_workspace_bytes.restype = sz
+    L.topk_sum_top_u32.argtypes = [vp, vp, vp, u64, u32, u32, u32, u64, vp, vp, vp, vp, vp, vp,
+                                   sz, vp]
+    L.topk_sample_size.argtypes = [i32, u64, u32, u32, ctypes.c_double, ctypes.c_double]
+    L.topk_sample_size.restype = ctypes.c_double
+    L.topk_sample_threshold.argtypes = [u64, ctypes.c_double]
+    L.topk_sample_threshold.restype = u64
     L.topk_strerror.argtypes = [i32]
     L.topk_strerror.restype = ctypes.c_char_p
     _lib = L
@@ -296,6 +307,78 @@ class Context:
         _check(lib().topk_trace_sample(self._h, _ptr(res["workspace"]), res["n"], tag, buf, cap,
                                        ctypes.byref(cnt), _stream(res["workspace"].device)))
         return list(buf[:min(cnt.value, cap)])
+
+
+    # ---- top-k most frequent objects (§7) and top-k sum aggregation (§8) ----
+
+    def frequent(self, keys, U, k, kstar=0, T=1 << 32, tables=False, workspace=None):
+        """The k most frequent objects of a 1-D int32/uint32 CUDA tensor of
+        objects in [0, U) (topk_frequent_u32): PAC when kstar = 0, else EC
+        counting kstar candidates exactly; sampling rate T / 2^32.
+
+        Returns a dict of device tensors: ``ids`` [k] and ``counts`` [k] (most
+        frequent first; PAC: sample counts, EC: exact counts), ``status`` and,
+        with ``tables``, ``sample_counts`` [U] and ``n_sampled`` [1]."""
+        if keys.dim() != 1 or not keys.is_cuda or keys.dtype not in (torch.int32, torch.uint32):
+            raise TopkError("frequent: keys must be a 1-D int32/uint32 CUDA tensor")
+        dev = keys.device
+        n = keys.numel()
+        if workspace is None:
+            nb = int(lib().topk_frequent_workspace_bytes(self._h, U))
+            workspace = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+        out = {"ids": torch.empty(k, dtype=torch.int32, device=dev),
+               "counts": torch.empty(k, dtype=torch.int32, device=dev),
+               "status": torch.empty(1, dtype=torch.int32, device=dev)}
+        if tables:
+            out["sample_counts"] = torch.empty(U, dtype=torch.int32, device=dev)
+            out["n_sampled"] = torch.empty(1, dtype=torch.int64, device=dev)
+        _check(lib().topk_frequent_u32(
+            self._h, _ptr(keys), n, U, k, kstar, int(T), _ptr(out["ids"]), _ptr(out["counts"]),
+            _ptr(out.get("sample_counts")), _ptr(out.get("n_sampled")), _ptr(out["status"]),
+            _ptr(workspace), workspace.numel(), _stream(dev)))
+        return out
+
+    def sum_top(self, keys, values, U, k, s, kstar=0, tables=False, workspace=None):
+        """The k keys with the largest sums of values (topk_sum_top_u32): the
+        input aggregated by key, a weighted sample of size about s, then PAC
+        (kstar = 0, values = sample counts) or the kstar most sampled keys
+        ranked by exact sum.  keys/values: 1-D int32/uint32 CUDA tensors.
+
+        Returns ``ids`` [k], ``vals`` [k] (int64), ``status`` and, with
+        ``tables``, ``sums`` [U] (int64) and ``samples`` [U]."""
+        for t in (keys, values):
+            if t.dim() != 1 or not t.is_cuda or t.dtype not in (torch.int32, torch.uint32):
+                raise TopkError("sum_top: keys and values must be 1-D int32/uint32 CUDA tensors")
+        dev = keys.device
+        n = keys.numel()
+        if workspace is None:
+            nb = int(lib().topk_sum_workspace_bytes(self._h, U))
+            workspace = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+        out = {"ids": torch.empty(k, dtype=torch.int32, device=dev),
+               "vals": torch.empty(k, dtype=torch.int64, device=dev),
+               "status": torch.empty(1, dtype=torch.int32, device=dev)}
+        if tables:
+            out["sums"] = torch.empty(U, dtype=torch.int64, device=dev)
+            out["samples"] = torch.empty(U, dtype=torch.int32, device=dev)
+        _check(lib().topk_sum_top_u32(
+            self._h, _ptr(keys), _ptr(values), n, U, k, kstar, int(s), _ptr(out["ids"]),
+            _ptr(out["vals"]), _ptr(out.get("sums")), _ptr(out.get("samples")),
+            _ptr(out["status"]), _ptr(workspace), workspace.numel(), _stream(dev)))
+        return out
+
+
+SAMPLE_PAC, SAMPLE_EC, SAMPLE_SUM = 0, 1, 2
+
+
+def sample_size(method, n, k=0, kstar=0, eps=1e-3, delta=1e-3):
+    """Expected sample size of §7 / §8 for an (eps, delta)-approximation
+    (topk_sample_size: SAMPLE_PAC, SAMPLE_EC or SAMPLE_SUM)."""
+    return float(lib().topk_sample_size(method, n, k, kstar, eps, delta))
+
+
+def sample_threshold(n, size):
+    """T = min(2^32, ceil(size 2^32 / n)): the sampling rate as a threshold."""
+    return int(lib().topk_sample_threshold(n, float(size)))
 
 
 _default = {}

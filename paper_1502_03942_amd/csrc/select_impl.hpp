@@ -819,6 +819,10 @@ __device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const P
     const u32 lane = lane_id();
     const u32 w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const u32 nwt = (u32)(((u64)n + WSPAN - 1) / WSPAN);
+    // A workgroup whose first generation holds no wave-tile has nothing to do
+    // (generation numbers only grow): it leaves before touching a counter, so
+    // a grid sized for the largest subproblem costs little on a small one.
+    if ((u64)blockIdx.x * SW_DW >= (u64)nwt) return;
 
     if (w == 0) {
         // ------------- control wave: one reservation per generation -------------

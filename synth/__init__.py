@@ -15,6 +15,9 @@ and the single-GPU workloads built on them:
 * ragged rows: lengths lognormal around a median, clipped; N(0,1) f32 keys;
   per-row k uniform in [1, min(len, k_max)]
 * dense N(0,1) f32 score matrices and upstream gradients
+* objects for the most-frequent-objects problem: Zipf(s = 1) over 2^20
+  values and a negative binomial (r = 1000, p = 0.05), the two input
+  distributions of §10.2; (key, value) pairs for the sum aggregation
 * f32 keys rich in special values (signed zeros, infinities, NaN payloads,
   subnormals, heavy repeats)
 """
@@ -99,3 +102,20 @@ def specials_f32(n, seed):
 def small_alphabet_u32(n, alphabet, seed):
     """u32 keys drawn from {0, ..., alphabet-1} (forces many ties)."""
     return _rng(seed).integers(0, alphabet, size=n, dtype=np.uint32)
+
+
+def negbin_u32(n, r, p, U, seed, chunk=1 << 24):
+    """Negative binomial(r, p) objects, clipped to [0, U)."""
+    rng = _rng(seed)
+    out = np.empty(n, np.uint32)
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        out[a:b] = np.minimum(rng.negative_binomial(r, p, size=b - a), U - 1)
+    return out
+
+
+def keyed_values(n, U, s, vmax, seed):
+    """(key, value) pairs: keys Zipf(s) over U, values uniform in [0, vmax]."""
+    keys = zipf_u32(n, s, U, seed)
+    values = _rng(seed + 1).integers(0, vmax + 1, size=n, dtype=np.uint32)
+    return keys, values
