@@ -22,6 +22,8 @@ TOPK_GRAPH = 16
 STATUS_OK = 0
 STATUS_INTERNAL = 1
 STATUS_BAD_ROW = 2
+STATUS_BAD_KEY = 4
+STATUS_SUM_RANGE = 8
 ROUND_EXACT = -2
 
 _lib = None
