@@ -197,3 +197,4 @@ def scatter_rows(grad_out, indices, n_cols):
 
 
 from . import freq  # noqa: E402,F401  (top-k most frequent objects and sum aggregation)
+from . import msselect  # noqa: E402,F401  (selection over sorted rows: msSelect, amsSelect)
