@@ -65,6 +65,8 @@ extern "C" {
 #define TOPK_STATUS_BAD_KEY 4u         /* frequent / sum: a key >= U was skipped      */
 #define TOPK_STATUS_SUM_RANGE 8u       /* sum: the sum of all values is >= 2^63, so
                                           the weighted sample is empty              */
+#define TOPK_STATUS_BAD_ARG 16u        /* sorted rows: k (or kmin) outside [1, n], or
+                                          positions beyond 32 bits; nothing written */
 
 typedef struct topk_ctx topk_ctx;
 
@@ -383,6 +385,54 @@ int topk_sum_top_u32(topk_ctx *ctx, const uint32_t *keys, const uint32_t *values
                      uint32_t U, uint32_t k, uint32_t kstar, uint64_t s, uint32_t *out_ids,
                      uint64_t *out_vals, uint64_t *sums, uint32_t *samples, uint32_t *status,
                      void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* ---- Selection over sorted sequences (§4.2 / Appendix A, §4.3) ----
+ *
+ * The p sequences are the rows of a CSR batch: keys[row_off[r] ..
+ * row_off[r + 1]) is row r, sorted ascending in the selection order (u32
+ * unsigned; f32 as for topk_select_f32; TOPK_LARGEST: sorted descending, and
+ * the largest are selected).  An object is identified by its position in
+ * keys[], so ties go by ascending position, and the selected objects form a
+ * prefix of every row: split[r] is that prefix's length.  Rows need not be
+ * of equal length; some may be empty.  Limits: 1 <= p <= 8192, row_off[p] <
+ * 2^32 (positions are 32-bit; checked on the device, which then writes
+ * TOPK_STATUS_BAD_ARG and nothing else), keys 4-byte and row_off 8-byte
+ * aligned.  One workgroup runs every round; the call is bound by the latency
+ * of its binary searches, not by bandwidth.  No workspace.
+ *
+ * topk_msselect_*: Algorithm "musel" (quickselect over sorted sequences):
+ * pivots uniform among the active objects (Philox4x32-10 at counter (round,
+ * i, 0, 6), key = the context seed), located in every row by binary search;
+ * d pivots per round (8 when p <= 1024, else 1; §4.3 "Multiple Concurrent
+ * Trials"), recursion between the best pivot below rank k and the best above
+ * (a pivot of rank exactly k ends it).  Writes split[p], *kth_pos (position of
+ * the object of rank k), *kth_key (its bits), *rounds (NULL or the rounds
+ * run), *status.  k in [1, n] (n = row_off[p] - row_off[0]).
+ *
+ * topk_amsselect_*: Algorithm "approxMusel": the k smallest objects for some
+ * k in [kmin, kmax] (1 <= kmin <= kmax; kmax above n counts as n).  Each
+ * round uses the min-based estimator (rate 1 - ((kmin-1)/kmax)^(1/(kmax-
+ * kmin+1))) when kmin < n_cur - kmax, else the max-based one; every row draws
+ * a geometric deviate per trial (Philox4x32-10 at counter (row, round, trial
+ * / 4, 7)), the trial's pivot is the minimum (maximum) of the rows' sampled
+ * objects, and the first trial whose count lies in [kmin, kmax] ends the
+ * call; otherwise the recursion continues between the best trials below and
+ * above.  After 64 rounds the call finishes exactly at rank kmin.  Writes
+ * split[p], *k_out (= the sum of split), *rounds, *status.
+ *
+ * All asynchronous on `stream`.  Return TOPK_OK, TOPK_E_INVALID or TOPK_E_HIP. */
+int topk_msselect_u32(topk_ctx *ctx, const uint32_t *keys, const uint64_t *row_off, uint32_t p,
+                      uint64_t k, uint32_t flags, uint32_t *split, uint32_t *kth_pos,
+                      uint32_t *kth_key, uint32_t *rounds, uint32_t *status, hipStream_t stream);
+int topk_msselect_f32(topk_ctx *ctx, const float *keys, const uint64_t *row_off, uint32_t p,
+                      uint64_t k, uint32_t flags, uint32_t *split, uint32_t *kth_pos,
+                      float *kth_key, uint32_t *rounds, uint32_t *status, hipStream_t stream);
+int topk_amsselect_u32(topk_ctx *ctx, const uint32_t *keys, const uint64_t *row_off, uint32_t p,
+                       uint64_t kmin, uint64_t kmax, uint32_t flags, uint32_t *split,
+                       uint64_t *k_out, uint32_t *rounds, uint32_t *status, hipStream_t stream);
+int topk_amsselect_f32(topk_ctx *ctx, const float *keys, const uint64_t *row_off, uint32_t p,
+                       uint64_t kmin, uint64_t kmax, uint32_t flags, uint32_t *split,
+                       uint64_t *k_out, uint32_t *rounds, uint32_t *status, hipStream_t stream);
 
 /* Sample sizes (host): the expected sample size for an (eps, delta)
  * approximation of §7 and §8 (0 < eps, 0 < delta < 1):

@@ -21,7 +21,7 @@ import math
 
 import numpy as np
 
-from . import select_sort, precedes
+from . import select_composite, select_sort, precedes
 
 
 def rows_sorted(keys, row_off, largest=False):
@@ -35,10 +35,11 @@ def rows_sorted(keys, row_off, largest=False):
     return True
 
 
-def ms_select(keys, row_off, k, largest=False):
+def ms_select(keys, row_off, k, largest=False, threads=0):
     """Object of global rank k and the split (selected prefix length of every
-    row) by a full sort of all objects.  Returns (kth position, split)."""
-    sel = select_sort(keys, k, largest)
+    row) by a full sort of all objects (threads > 0: the composite-key form
+    of the sort on that many threads).  Returns (kth position, split)."""
+    sel = select_composite(keys, k, largest, threads) if threads else select_sort(keys, k, largest)
     row_of = np.searchsorted(np.asarray(row_off, np.int64), sel.astype(np.int64), side="right") - 1
     split = np.bincount(row_of, minlength=len(row_off) - 1).astype(np.uint32)
     return int(sel[-1]), split

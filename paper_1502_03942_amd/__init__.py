@@ -24,6 +24,7 @@ STATUS_INTERNAL = 1
 STATUS_BAD_ROW = 2
 STATUS_BAD_KEY = 4
 STATUS_SUM_RANGE = 8
+STATUS_BAD_ARG = 16
 ROUND_EXACT = -2
 
 _lib = None
@@ -95,6 +96,12 @@ def lib():
     L.topk_sample_size.restype = ctypes.c_double
     L.topk_sample_threshold.argtypes = [u64, ctypes.c_double]
     L.topk_sample_threshold.restype = u64
+    ms = [vp, vp, vp, u32, u64, u32, vp, vp, vp, vp, vp, vp]
+    L.topk_msselect_u32.argtypes = ms
+    L.topk_msselect_f32.argtypes = ms
+    ams = [vp, vp, vp, u32, u64, u64, u32, vp, vp, vp, vp, vp]
+    L.topk_amsselect_u32.argtypes = ams
+    L.topk_amsselect_f32.argtypes = ams
     L.topk_strerror.argtypes = [i32]
     L.topk_strerror.restype = ctypes.c_char_p
     _lib = L
@@ -366,6 +373,56 @@ class Context:
             self._h, _ptr(keys), _ptr(values), n, U, k, kstar, int(s), _ptr(out["ids"]),
             _ptr(out["vals"]), _ptr(out.get("sums")), _ptr(out.get("samples")),
             _ptr(out["status"]), _ptr(workspace), workspace.numel(), _stream(dev)))
+        return out
+
+
+    # ---- selection over sorted rows: msSelect (App. A), amsSelect (§4.3) ----
+
+    def _ms_keys(self, keys, row_off):
+        if keys.dim() != 1 or not keys.is_cuda:
+            raise TopkError("keys must be a 1-D CUDA tensor")
+        if row_off.dtype not in (torch.int64, torch.uint64) or not row_off.is_cuda:
+            raise TopkError("row_off must be an int64 CUDA tensor [p + 1]")
+        if keys.dtype == torch.float32:
+            return True
+        if keys.dtype in (torch.int32, torch.uint32):
+            return False
+        raise TopkError("keys must be float32 or uint32/int32 bits")
+
+    def msselect(self, keys, row_off, k, largest=False):
+        """The object of rank k among sorted rows (topk_msselect_*): rows of a
+        CSR batch, each sorted in the selection order.  Returns device tensors
+        ``split`` [p] (selected prefix length per row), ``kth_pos``,
+        ``kth_key``, ``rounds``, ``status``."""
+        f32 = self._ms_keys(keys, row_off)
+        p = row_off.numel() - 1
+        dev = keys.device
+        out = {"split": torch.empty(p, dtype=torch.int32, device=dev),
+               "kth_pos": torch.empty(1, dtype=torch.int32, device=dev),
+               "kth_key": torch.empty(1, dtype=keys.dtype, device=dev),
+               "rounds": torch.zeros(1, dtype=torch.int32, device=dev),
+               "status": torch.empty(1, dtype=torch.int32, device=dev)}
+        fn = lib().topk_msselect_f32 if f32 else lib().topk_msselect_u32
+        _check(fn(self._h, _ptr(keys), _ptr(row_off), p, int(k), TOPK_LARGEST if largest else 0,
+                  _ptr(out["split"]), _ptr(out["kth_pos"]), _ptr(out["kth_key"]),
+                  _ptr(out["rounds"]), _ptr(out["status"]), _stream(dev)))
+        return out
+
+    def amsselect(self, keys, row_off, kmin, kmax, largest=False):
+        """The k smallest objects of sorted rows for some k in [kmin, kmax]
+        (topk_amsselect_*).  Returns ``split`` [p], ``k`` (the k chosen),
+        ``rounds``, ``status``."""
+        f32 = self._ms_keys(keys, row_off)
+        p = row_off.numel() - 1
+        dev = keys.device
+        out = {"split": torch.empty(p, dtype=torch.int32, device=dev),
+               "k": torch.empty(1, dtype=torch.int64, device=dev),
+               "rounds": torch.zeros(1, dtype=torch.int32, device=dev),
+               "status": torch.empty(1, dtype=torch.int32, device=dev)}
+        fn = lib().topk_amsselect_f32 if f32 else lib().topk_amsselect_u32
+        _check(fn(self._h, _ptr(keys), _ptr(row_off), p, int(kmin), int(kmax),
+                  TOPK_LARGEST if largest else 0, _ptr(out["split"]), _ptr(out["k"]),
+                  _ptr(out["rounds"]), _ptr(out["status"]), _stream(dev)))
         return out
 
 
