@@ -140,8 +140,9 @@ __global__ __launch_bounds__(MS_THREADS) void k_msselect(MsArgs a)
         u32 total;
         const u32 excl = block_excl_scan<MS_THREADS>(mine, sh.scan, &total);
         if (tid < MS_ITEMS) {
+            // exact: every pivot is written by its owner; flexible: set with
+            // the estimator below (it depends on the mode)
             sh.cnt[tid] = 0u;
-            sh.piv[tid] = exact ? ~0ull : 0ull;
             has[tid] = 0u;
         }
         if (exact && total == 1) {
@@ -150,7 +151,7 @@ __global__ __launch_bounds__(MS_THREADS) void k_msselect(MsArgs a)
             for (int q = 0; q < QR; ++q) {
                 if (!own[q]) continue;
                 const bool one = hi[q] - lo[q] == 1;
-                if (one) {
+                if (one && a.kth_pos) {             // (the flexible call has no k-th object output)
                     const u32 pos = (u32)(base[q] + lo[q]);
                     *a.kth_pos = pos;
                     *a.kth_key = a.keys[pos];
@@ -158,7 +159,6 @@ __global__ __launch_bounds__(MS_THREADS) void k_msselect(MsArgs a)
                 a.split[tid + (u32)q * MS_THREADS] = lo[q] + (one ? 1u : 0u);
             }
             if (tid == 0 && a.rounds) *a.rounds = round;
-            if (FLEX && tid == 0) *a.k_out = k_cur + (u64)0;   // overwritten below
             if (FLEX) {
                 // only reached after the flexible rounds were spent: k = kmin
                 u32 s = 0;
@@ -213,6 +213,9 @@ __global__ __launch_bounds__(MS_THREADS) void k_msselect(MsArgs a)
                 else rho = 1.0 - pow((dn - dmax) / (dn - dmin + 1.0), 1.0 / (dmax - dmin + 1.0));
                 sh.rho = rho;
                 sh.maxmode = mx ? 1 : 0;
+                // the identity of the trial reductions: -inf for the maximum,
+                // +inf for the minimum
+                for (int i = 0; i < MS_ITEMS; ++i) sh.piv[i] = mx ? 0ull : ~0ull;
             }
             __syncthreads();
             const double rho = sh.rho;
@@ -333,7 +336,7 @@ __global__ __launch_bounds__(MS_THREADS) void k_msselect(MsArgs a)
                 s += sp;
             }
             if (tid == 0) {
-                if (exact) {
+                if (exact && a.kth_pos) {           // (the flexible call has no k-th object output)
                     const u32 pos = (u32)sh.piv[hit];
                     *a.kth_pos = pos;
                     *a.kth_key = a.keys[pos];
