@@ -433,6 +433,142 @@ def bench_rows(args):
             "bwd_frac": round(bb / (bwd * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
 
 
+def _timed(fn, reps=10):
+    """Median of reps HIP-event-timed calls (ms) on the current stream."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    for _ in range(2):
+        fn()
+    t = []
+    for _ in range(reps):
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        t.append(e0.elapsed_time(e1))
+    return float(np.median(t))
+
+
+def bench_frequent(args):
+    """Top-k most frequent objects (PAC and EC) and top-k sum aggregation on
+    the workloads of the paper's most-frequent-objects experiment, one device:
+    n = 2^28 objects, Zipf(1) over 2^20 values and negative binomial (r = 1000,
+    p = 0.05), k = 32, (eps, delta) = (3e-4, 1e-4).  Results are checked
+    against the oracle outside the timed region."""
+    import torch
+    import paper_1502_03942_amd as tk
+    import synth
+    import oracle
+
+    dev = torch.device("cuda:0")
+    n, k, eps, delta = 1 << 28, 32, 3e-4, 1e-4
+    out = {}
+    for name, gen, U in (("zipf1_2p20", lambda: synth.zipf_u32(n, 1.0, 1 << 20, 7), 1 << 20),
+                         ("negbin_r1000_p005", lambda: synth.negbin_u32(n, 1000, 0.05, 1 << 15, 8),
+                          1 << 15)):
+        log("frequent: generating %s" % name)
+        keys_np = gen()
+        keys = torch.from_numpy(keys_np.view(np.int32)).to(dev)
+        ctx = tk.Context(0, seed=0x5EED)
+        nb = int(tk.lib().topk_frequent_workspace_bytes(ctx._h, U))
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        res = {}
+        for method, kstar in (("pac", 0), ("ec", k)):
+            size = tk.sample_size(tk.SAMPLE_PAC if kstar == 0 else tk.SAMPLE_EC, n, k, kstar, eps, delta)
+            T = tk.sample_threshold(n, size)
+            ms = _timed(lambda: ctx.frequent(keys, U, k, kstar=kstar, T=T, workspace=ws))
+            r = ctx.frequent(keys, U, k, kstar=kstar, T=T, workspace=ws)
+            torch.cuda.synchronize()
+            ids = r["ids"].cpu().numpy().view(np.uint32)
+            cnt = r["counts"].cpu().numpy().view(np.uint32)
+            if not args.no_check:
+                if kstar == 0:
+                    rid, rc_, _ = oracle.freq.pac(keys_np, U, k, T, 0x5EED)
+                else:
+                    rid, rc_, _ = oracle.freq.ec(keys_np, U, k, kstar, T, 0x5EED)
+                if not (np.array_equal(ids, rid) and np.array_equal(cnt, rc_.astype(np.uint32))):
+                    raise SystemExit("frequent %s %s: result differs from the oracle" % (name, method))
+            passes = 1 if kstar == 0 else 2
+            res[method] = {"ms": round(ms, 4), "gkeys_s": round(n / (ms * 1e-3) / 1e9, 2),
+                           "rho": round(min(1.0, T / 2.0**32), 6),
+                           "hbm_frac_min_bytes": round(4 * n * passes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+                           "check": None if args.no_check else "equal to the oracle"}
+            log("frequent %s %s: %.4f ms" % (name, method, ms))
+        out[name] = res
+        del keys
+    # sum aggregation: 2^26 (key, value) pairs, keys Zipf(1) over 2^20, values in [0, 1000]
+    nn, U = 1 << 26, 1 << 20
+    keys_np, vals_np = synth.keyed_values(nn, U, 1.0, 1000, 11)
+    kd = torch.from_numpy(keys_np.view(np.int32)).to(dev)
+    vd = torch.from_numpy(vals_np.view(np.int32)).to(dev)
+    ctx = tk.Context(0, seed=0x5EED)
+    ws = torch.empty(int(tk.lib().topk_sum_workspace_bytes(ctx._h, U)), dtype=torch.uint8, device=dev)
+    s_size = int(tk.sample_size(tk.SAMPLE_SUM, nn, k, 0, eps, delta))
+    res = {}
+    for method, kstar in (("pac", 0), ("exact_sums", 4 * k)):
+        ms = _timed(lambda: ctx.sum_top(kd, vd, U, k, s_size, kstar=kstar, workspace=ws))
+        r = ctx.sum_top(kd, vd, U, k, s_size, kstar=kstar, workspace=ws)
+        torch.cuda.synchronize()
+        if not args.no_check:
+            if kstar == 0:
+                rid, rv = oracle.freq.sum_pac(keys_np, vals_np, U, k, s_size, 0x5EED)
+            else:
+                rid, rv = oracle.freq.sum_ec(keys_np, vals_np, U, k, kstar, s_size, 0x5EED)
+            if not (np.array_equal(r["ids"].cpu().numpy().view(np.uint32), rid) and
+                    np.array_equal(r["vals"].cpu().numpy().view(np.uint64), rv.astype(np.uint64))):
+                raise SystemExit("sum aggregation %s: result differs from the oracle" % method)
+        res[method] = {"ms": round(ms, 4), "gpairs_s": round(nn / (ms * 1e-3) / 1e9, 2),
+                       "hbm_frac_min_bytes": round(8 * nn / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+        log("sum %s: %.4f ms" % (method, ms))
+    out["sum_aggregation_2p26_pairs"] = dict(res, sample_size=s_size)
+    out["workload"] = ("n = 2^28 objects per distribution, k = 32, (eps, delta) = (3e-4, 1e-4): "
+                       "PAC at the rate of the sample-size equation (rho = 1 here), EC with k* = 32 "
+                       "at the rate of Lemma topkec; sum aggregation on 2^26 pairs")
+    return out
+
+
+def bench_msselect(args):
+    """Selection over 1024 sorted rows of 2^18 f32 keys (2^28 keys): msSelect
+    for k in {2^10, 2^20, 2^27}, amsSelect for [k - k/8, k].  Latency-bound
+    (dependent binary searches): reported in microseconds per call."""
+    import torch
+    import paper_1502_03942_amd as tk
+    import synth
+    import oracle
+
+    dev = torch.device("cuda:0")
+    p, L = 1024, 1 << 18
+    keys_np = synth.uniform_f32_grid(p * L, 9).reshape(p, L)
+    keys_np.sort(axis=1)
+    keys_np = keys_np.reshape(-1)
+    off_np = (np.arange(p + 1, dtype=np.int64) * L)
+    keys = torch.from_numpy(keys_np).to(dev)
+    off = torch.from_numpy(off_np).to(dev)
+    ctx = tk.Context(0, seed=0x5EED)
+    out = {"workload": "1024 rows of 2^18 sorted f32 keys (uniform on [0,1), 2^-24 grid, seed 9)"}
+    for k in (1 << 10, 1 << 20, 1 << 27):
+        ms = _timed(lambda: ctx.msselect(keys, off, k))
+        r = ctx.msselect(keys, off, k)
+        ra = ctx.amsselect(keys, off, k - k // 8, k)
+        ms_a = _timed(lambda: ctx.amsselect(keys, off, k - k // 8, k))
+        torch.cuda.synchronize()
+        if not args.no_check:
+            kth, split = oracle.msselect.ms_select(keys_np, off_np, k, False, threads=16)
+            if not (np.array_equal(r["split"].cpu().numpy().astype(np.int64), split.astype(np.int64))
+                    and int(r["kth_pos"].item()) == kth):
+                raise SystemExit("msselect k=%d: result differs from the oracle" % k)
+            if oracle.msselect.ams_check(keys_np, off_np, k - k // 8, k,
+                                         ra["split"].cpu().numpy().astype(np.int64)) != 0:
+                raise SystemExit("amsselect k=%d: invalid result" % k)
+        out[str(k)] = {"msselect_us": round(ms * 1e3, 1), "msselect_rounds": int(r["rounds"].item()),
+                       "amsselect_us": round(ms_a * 1e3, 1), "amsselect_rounds": int(ra["rounds"].item()),
+                       "amsselect_k": int(ra["k"].item())}
+        log("msselect k=%d: %.1f us (%d rounds); amsselect: %.1f us" %
+            (k, ms * 1e3, int(r["rounds"].item()), ms_a * 1e3))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -451,6 +587,9 @@ def main():
                     help="only the batched form (no JSON line: a profiling aid)")
     ap.add_argument("--rows-only", action="store_true",
                     help="only the row-wise forward and backward (no JSON line: a profiling aid)")
+    ap.add_argument("--frequent-only", action="store_true",
+                    help="only the most-frequent-objects, sum-aggregation and sorted-rows "
+                         "selections (no JSON line: a profiling aid)")
     ap.add_argument("--single-only", action="store_true",
                     help="only the single-instance selection (skip the batched and row forms)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -475,11 +614,17 @@ def main():
     if args.rows_only:
         log("rows: %s" % json.dumps(bench_rows(args)))
         return
+    if args.frequent_only:
+        log("frequent: %s" % json.dumps(bench_frequent(args)))
+        log("msselect: %s" % json.dumps(bench_msselect(args)))
+        return
     out = bench_select(args)
     if not args.single_only:
         out["configs"] = bench_configs(args, {p["k"]: p["ms"] for p in out["per_k"]})
         out["batched"] = bench_batched(args)
         out["rows_topk"] = bench_rows(args)
+        out["frequent"] = bench_frequent(args)
+        out["sorted_rows"] = bench_msselect(args)
     print(json.dumps(out), flush=True)
 
 
