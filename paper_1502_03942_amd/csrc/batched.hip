@@ -76,7 +76,6 @@ struct BtShared {
     u32 scan[BT_WAVES];
     u32 wt[2][BT_WAVES];        // sweep: per-wave (|a| | |b| << 16) of a step, by step parity
     u32 next;                   // next row position handed to this workgroup
-    u32 bfill;                  // sampled short row: band pairs appended
 };
 
 struct BtArgs {
@@ -669,101 +668,6 @@ __device__ __forceinline__ u64 bt_reg_row(const u32 *__restrict__ row, u32 len, 
     return tau;
 }
 
-// A short row by one round of §2 inside the workgroup, the keys staying in
-// registers: pivots at sample ranks k s / len -/+ Delta (R4) from a
-// stratified sample (every thread contributes the key of one of its slots,
-// picked by a hash of the row and the thread), one pass that counts the
-// keys below L and appends the band [L, R] to LDS, the exact rank of
-// k - |below L| among the band, then the column-order emit of every key at or
-// below it.  A miss or a band too wide for LDS falls back to the exact
-// register select, so the result never depends on the sample.  Used for rows
-// of more than BT_THREADS * 4 keys (every thread then has a slot to sample).
-template <bool LARGEST, int M>
-__device__ __forceinline__ u64 bt_reg_row_sampled(const u32 *__restrict__ row, u32 len, u32 k,
-                                                  u32 *out, BtShared &sh, u64 seed, u32 rowid,
-                                                  u32 c_num)
-{
-    constexpr u32 S = BT_THREADS;               // sample size (one per thread)
-    constexpr u32 BAND_CAP = BT_CAP - S;         // band slots after the sample
-    const u32 tid = bt_tid(), lane = tid & (WAVE - 1);
-    const u32 w = __builtin_amdgcn_readfirstlane(tid / WAVE);
-    const u32 jn = (len + BT_THREADS - 1) / BT_THREADS;
-    u32 o[M];
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-        const u32 col = (u32)j * BT_THREADS + tid;
-        o[j] = (u32)j < jn ? row[col < len ? col : len - 1] : 0u;
-    }
-#pragma unroll
-    for (int j = 0; j < M; ++j) o[j] = key_ord<true, LARGEST>(o[j]);
-    // the sample: slot js of this thread (it has `mine` >= 1 valid slots)
-    const u32 mine = (len - tid + BT_THREADS - 1) / BT_THREADS;
-    u32 h = (tid * 0x9E3779B1u) ^ (rowid * 0x85EBCA6Bu) ^ (u32)seed ^ (u32)(seed >> 32);
-    h ^= h >> 15;
-    h *= 0x2C1B3C6Du;
-    h ^= h >> 12;
-    const u32 js = h % mine;
-    u64 smp = 0;
-#pragma unroll
-    for (int j = 0; j < M; ++j)
-        if ((u32)j == js) smp = pack(o[j], (u32)j * BT_THREADS + tid);
-    sh.buf[tid] = smp;
-    if (tid == 0) sh.bfill = 0u;
-    lds_sync();
-    i64 lo, hi;
-    pivot_ranks(S, k, len, c_num, lo, hi);
-    const bool hl = lo >= 0, hr = hi < (i64)S;
-    u64 piv[2];
-    {
-        const u64 rk[2] = {hl ? (u64)lo : 0ull, hr ? (u64)hi : 0ull};
-        const bool ac[2] = {hl, hr};
-        bt_select([&](u32 i) -> u64 { return sh.buf[i]; }, S, 64, rk, ac, piv, sh);
-    }
-    const u64 L = hl ? uniform64(piv[0]) : 0ull;
-    const u64 R = hr ? uniform64(piv[1]) : ~0ull;
-    // one pass: |below L| by ballots, the band appended to LDS after the sample
-    u32 na = 0;
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-        if ((u32)j < jn) {
-            const u32 col = (u32)j * BT_THREADS + tid;
-            const u64 c = pack(o[j], col);
-            const bool ok = col < len;
-            const bool below = hl && c < L;
-            const bool ia = ok && below;
-            const bool ib = ok && !below && !(hr && c > R);
-            na += (u32)__popcll(ballot(ia));
-            const u64 mb = ballot(ib);
-            if (mb) {
-                u32 base = 0;
-                if (lane == 0) base = atomicAdd(&sh.bfill, (u32)__popcll(mb));
-                base = __builtin_amdgcn_readfirstlane(base);
-                const u32 q = base + mbcnt(mb);
-                if (ib && q < BAND_CAP) sh.buf[S + q] = c;
-            }
-        }
-    }
-    if (lane == 0) sh.wt[0][w] = na;
-    lds_sync();
-    u32 n_a = 0;
-#pragma unroll
-    for (int v = 0; v < BT_WAVES; ++v) n_a += __builtin_amdgcn_readfirstlane(sh.wt[0][v]);
-    const u32 n_b = __builtin_amdgcn_readfirstlane(sh.bfill);
-    u64 tau;
-    if (n_a < k && (u64)n_a + n_b >= k && n_b <= BAND_CAP) {
-        const int top = (hl && hr) ? ((L == R) ? 0 : 64 - __clzll((long long)(L ^ R))) : 64;
-        const u64 rk[2] = {(u64)(k - n_a - 1), 0ull};
-        const bool one[2] = {true, false};
-        u64 t2[2];
-        bt_select([&](u32 i) -> u64 { return sh.buf[S + i]; }, n_b, top, rk, one, t2, sh);
-        tau = t2[0];
-    } else {
-        tau = bt_reg_select<M>(o, len, k - 1, sh);
-    }
-    bt_reg_emit<M>(o, len, tau, out, k, sh);
-    return tau;
-}
-
 template <bool LARGEST>
 __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
 {
@@ -797,12 +701,10 @@ __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
         reg_tau = bt_reg_row<LARGEST, BT_REG_KEYS / 8 / BT_THREADS>(row, len, k, out, sh);
         reg_done = true;
     } else if (len <= BT_REG_KEYS / 2) {
-        reg_tau = bt_reg_row_sampled<LARGEST, BT_REG_KEYS / 2 / BT_THREADS>(
-            row, len, k, out, sh, a.seed, r, a.c_cls[cls]);
+        reg_tau = bt_reg_row<LARGEST, BT_REG_KEYS / 2 / BT_THREADS>(row, len, k, out, sh);
         reg_done = true;
     } else if (len <= BT_REG_KEYS) {
-        reg_tau = bt_reg_row_sampled<LARGEST, BT_REG_KEYS / BT_THREADS>(
-            row, len, k, out, sh, a.seed, r, a.c_cls[cls]);
+        reg_tau = bt_reg_row<LARGEST, BT_REG_KEYS / BT_THREADS>(row, len, k, out, sh);
         reg_done = true;
     } else {
         u32 c_num = a.c_cls[cls];
