@@ -318,15 +318,17 @@ def bench_batched(args):
         ctx.load_tuning(args.tuning_prefix + "batched.json")
         log("tuning loaded from %sbatched.json" % args.tuning_prefix)
     elif not args.no_tune:
-        # the autotuner (setup, untimed): sample size and spread per length
-        # class of the sampling path, workgroups per CU
+        # the autotuner (setup, untimed): sample size, spread and sweep tile
+        # per length class of the sampling path, attempts, workgroups per CU
         ctx.tune_batched(keys, off, kk, reps=3)
     if args.tuning_prefix or not args.no_tune:
         for c in range(34):
             sv = ctx.get_param("bt_s_target@%d" % c)
             if sv >= 0:
-                tuned["class_%d" % c] = {"bt_s_target": sv, "bt_c_num": ctx.get_param("bt_c_num@%d" % c)}
+                tuned["class_%d" % c] = {"bt_s_target": sv, "bt_c_num": ctx.get_param("bt_c_num@%d" % c),
+                                         "bt_tile": ctx.get_param("bt_tile@%d" % c)}
         tuned["bt_wg_per_cu"] = ctx.get_param("bt_wg_per_cu")
+        tuned["bt_attempts"] = ctx.get_param("bt_attempts")
         log("tuned: %s" % tuned)
         if args.save_tuning_prefix:
             ctx.save_tuning(args.save_tuning_prefix + "batched.json")

@@ -221,7 +221,9 @@ int topk_stream_read(topk_ctx *ctx, const uint32_t *keys, uint64_t n, uint32_t *
  *   "bt_c_num"       12  pivot spread (as c_num above); 4..4096
  *   "bt_wg_per_cu"    4  resident workgroups per CU of the persistent grid; 1..8
  *   "bt_attempts"     4  sampling attempts before the exact fallback; 1..16
- *   "bt_s_target@C", "bt_c_num@C"  the same for the rows of length class C
+ *   "bt_tile"        16  keys per thread per step of the fast sweep: 8 or 16
+ *                        (a tile of 2048 or 4096 keys)
+ *   "bt_s_target@C", "bt_c_num@C", "bt_tile@C"  the same for the rows of length class C
  *                        only (lengths [2^(C-1), 2^C), 0 <= C < 34); -1
  *                        (default) falls back to the value above
  *   "bt_fast"         1  1: a row whose expected candidates (keys up to the
@@ -246,7 +248,7 @@ int topk_select_batched_f32(topk_ctx *ctx, const float *keys, const uint64_t *ro
  * cannot allocate device memory or pass a workspace (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation).  Same
  * arguments, results and kernels, without workspace and ws_bytes: the
- * workspace is a file-scope device array of the library (4 MiB + 768 bytes on
+ * workspace is a file-scope device array of the library (4 MiB + 70,144 bytes on
  * every device the library runs on, held until the process ends), enough for
  * rows <= 1,048,576.  No call allocates anything (no hipMalloc, no hipFree,
  * no allocating library routine); the library looks the array's device
@@ -270,8 +272,9 @@ int topk_select_batched_f32_noalloc(topk_ctx *ctx, const float *keys, const uint
  * that class is timed (median of `reps` calls, HIP events on `stream`) under
  * each pair bt_s_target in {256, 512, 1024, 2048} x bt_c_num in
  * {8, 12, 16, 24}; the fastest pair becomes the class's "bt_s_target@C" /
- * "bt_c_num@C".  Then "bt_wg_per_cu" in {2, 3, 4} is timed over the whole
- * batch and the fastest kept.  Blocks the host until the stream is idle.
+ * "bt_c_num@C", and under it the faster of "bt_tile@C" in {8, 16}.  Then
+ * "bt_attempts" in {1, 2, 4, 8} and "bt_wg_per_cu" in {2, 3, 4} are timed
+ * over the whole batch and the fastest of each kept.  Blocks the host until the stream is idle.
  * Returns TOPK_OK, the errors of topk_select_batched_f32, or TOPK_E_INVALID
  * for reps outside 1..100. */
 int topk_tune_batched_f32(topk_ctx *ctx, const float *keys, const uint64_t *row_off,

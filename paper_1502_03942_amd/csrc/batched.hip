@@ -2,7 +2,8 @@
 // persistent launch (§1: many similar selections solved together).
 //
 // Rows are ordered longest first (a counting sort by floor(log2 len)) and
-// handed out from a queue to a persistent grid of 256-thread workgroups: one
+// handed out from eight queues (one per XCD, each serving every eighth
+// position of the order) to a persistent grid of 256-thread workgroups: one
 // row per grab for the long rows, 16 per grab afterwards.  One workgroup
 // solves a row by the sampling method of §2 with the workgroup as the
 // machine:
@@ -57,14 +58,19 @@ constexpr int BT_BITS = 10;                     // radix digit
 constexpr u32 BT_BINS = 1u << BT_BITS;
 constexpr int BT_BPT = (int)BT_BINS / BT_THREADS;   // histogram bins per thread in the scan
 constexpr int BT_SEG = 16;                      // sample slots per thread (expected bt_s_target / 256 <= 8)
-constexpr int BT_IPT = 16;                      // keys per thread per sweep step
+constexpr int BT_IPT = 16;                      // keys per thread per step of the general sweep
 constexpr u32 BT_STEP = BT_THREADS * BT_IPT;
 constexpr int BT_NCLS = 34;                     // length classes 0 (empty) .. 33
 constexpr int BT_HIST_THREADS = 1024;
 constexpr u32 BT_REG = BT_CAP / BT_WAVES;       // fast sweep: candidate slots per wave
 constexpr u32 BT_FAST_NUM = 7, BT_FAST_DEN = 10; // fast sweep when expected candidates <= 0.7 BT_CAP
-constexpr u32 BT_Q1 = 4096;                     // queue: rows taken one at a time first
-constexpr u32 BT_QCHUNK = 16;                   // then this many per grab
+constexpr u32 BT_NQ = 8;                        // row queues of each mode: one per XCD
+constexpr u32 BT_QSTRIDE = 1088;                // words between two queue counters (4 KiB + 256 bytes)
+constexpr u32 BT_Q1 = 64;                       // per queue: positions taken one at a time first
+constexpr u32 BT_QCHUNK = 4;                    // then this many per grab
+constexpr u32 BT_WAVE_CLS = 11;                 // rows of classes <= this (< 2048 keys): one wave each
+constexpr u32 BT_WAVE_M = 32;                   // their keys per lane at most
+constexpr u32 BT_WQCHUNK = 2;                   // rows per grab of a wave
 
 struct BtShared {
     u64 buf[BT_CAP];
@@ -75,8 +81,16 @@ struct BtShared {
     u32 ccount[2], sel_bin[2], sel_before[2], sel_count[2];
     u32 scan[BT_WAVES];
     u32 wt[2][BT_WAVES];        // sweep: per-wave (|a| | |b| << 16) of a step, by step parity
-    u32 next;                   // next row position handed to this workgroup
+    u32 next;                   // the workgroup's last grab from a queue
+    u32 n_wg;                   // order positions [0, n_wg): rows solved by the workgroup
 };
+
+// LDS of one wave in the wave-per-row mode (inside BtShared::buf).
+struct BtWaveLds {
+    u32 hist[BT_BINS];
+    u64 cand[WAVE];
+};
+static_assert(sizeof(BtWaveLds) * BT_WAVES <= sizeof(u64) * BT_CAP, "wave LDS fits the band buffer");
 
 struct BtArgs {
     const u32 *keys;
@@ -90,6 +104,7 @@ struct BtArgs {
     u32 attempts, fast;
     u32 cls_lo, cls_hi;                 // only rows of these length classes
     u32 s_cls[BT_NCLS], c_cls[BT_NCLS]; // sample size and spread by length class
+    u32 t_cls[BT_NCLS];                 // fast-sweep tile (keys per thread per step: 8 or 16)
 };
 
 __device__ __forceinline__ u32 len_class(u64 len)
@@ -309,21 +324,26 @@ __device__ __forceinline__ int bt_sample(u32 t, u64 len, u32 s_target, u64 seed,
     const u64 e0 = s0 + L < len ? s0 + L : len;
     if (s0 >= e0) return 0;
     const float inv = 1.0f / log1pf(-rho);
-    u32 w[BT_SEG];
-#pragma unroll
-    for (int j = 0; j < BT_SEG; j += 4) {
-        const uint4 r4 = philox4x32_10(make_uint4((u32)(j >> 2), t, tag, row), (u32)seed, (u32)(seed >> 32));
-        w[j] = r4.x; w[j + 1] = r4.y; w[j + 2] = r4.z; w[j + 3] = r4.w;
-    }
     u64 p = s0 - 1;
     int cnt = 0;
+    bool past = false;               // this segment is done
 #pragma unroll
-    for (int j = 0; j < BT_SEG; ++j) {
-        const float u = ((float)(w[j] >> 8) + 0.5f) * (1.0f / 16777216.0f);
-        const float q = __logf(u) * inv;
-        const u64 skip = q >= (float)L ? L + 1 : 1 + (u64)q;
-        p += skip;
-        if (p < e0) { pos[j] = (u32)p; cnt = j + 1; }
+    for (int j0 = 0; j0 < BT_SEG; j0 += 4) {
+        if (ballot(!past) == 0) break;   // every segment of the wave is done
+        const uint4 r4 = philox4x32_10(make_uint4((u32)(j0 >> 2), t, tag, row), (u32)seed, (u32)(seed >> 32));
+        const u32 w[4] = {r4.x, r4.y, r4.z, r4.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int j = j0 + i;
+            const float u = ((float)(w[i] >> 8) + 0.5f) * (1.0f / 16777216.0f);
+            const float q = __logf(u) * inv;
+            const u64 skip = q >= (float)L ? L + 1 : 1 + (u64)q;
+            if (!past) {
+                p += skip;
+                if (p < e0) { pos[j] = (u32)p; cnt = j + 1; }
+                else past = true;
+            }
+        }
     }
     return cnt;
 }
@@ -339,14 +359,14 @@ __device__ __forceinline__ float ord_value(u32 o)
 template <bool LARGEST>
 __device__ __forceinline__ bool ord_is_nan(u32 o) { return (LARGEST ? ~o : o) == 0xFFFFFFFFu; }
 
-// 16 keys per lane of one sweep step: columns s0 + (16 j + 4 w) ... interleaved
-// so that wave w holds columns s0 + (j * BT_WAVES + w) * 64 + lane.
-template <bool GUARD>
+// IPT keys per lane of one sweep step (the tile: BT_THREADS * IPT keys),
+// interleaved so that wave w holds columns s0 + (j * BT_WAVES + w) * 64 + lane.
+template <bool GUARD, int IPT>
 __device__ __forceinline__ void bt_load_step(const u32 *__restrict__ row, u32 s0, u32 len, u32 w,
-                                             u32 lane, u32 (&x)[16])
+                                             u32 lane, u32 (&x)[IPT])
 {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
+    for (int j = 0; j < IPT; ++j) {
         const u32 col = s0 + ((u32)j * BT_WAVES + w) * WAVE + lane;
         x[j] = row[GUARD ? (col < len ? col : len - 1) : col];
     }
@@ -357,12 +377,12 @@ __device__ __forceinline__ void bt_load_step(const u32 *__restrict__ row, u32 s0
 // the key order agree, -0 and +0 included) are appended with their column to
 // the wave's own LDS region; `na` counts those below the lower pivot L.  The
 // regions of the waves are independent, so the sweep needs no barrier.
-template <bool LARGEST, bool TAIL>
-__device__ __forceinline__ void bt_fast_step(const u32 (&x)[16], u32 s0, u32 len, u32 w, u32 lane,
+template <bool LARGEST, bool TAIL, int IPT>
+__device__ __forceinline__ void bt_fast_step(const u32 (&x)[IPT], u32 s0, u32 len, u32 w, u32 lane,
                                              float fL, float fR, u64 *reg, u32 &cnt, u32 &na)
 {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
+    for (int j = 0; j < IPT; ++j) {
         const u32 col = s0 + ((u32)j * BT_WAVES + w) * WAVE + lane;
         const float f = __uint_as_float(x[j]);
         // largest: NaN keys come first, so "not below R" and "not at or below L"
@@ -389,34 +409,36 @@ __device__ __forceinline__ void bt_fast_step(const u32 (&x)[16], u32 s0, u32 len
     }
 }
 
-// The whole fast sweep of one wave over the row, loads one step ahead.
-template <bool LARGEST>
+// The whole fast sweep of one wave over the row, loads one step ahead
+// (IPT keys per lane per step: the tile size the autotuner picks).
+template <bool LARGEST, int IPT>
 __device__ __forceinline__ void bt_fast_sweep(const u32 *__restrict__ row, u32 len, float fL, float fR, bool hl,
                               u64 *reg, u32 &cnt_out, u32 &na_out)
 {
+    constexpr u32 STEP = BT_THREADS * IPT;
     const u32 tid = bt_tid();
     const u32 w = __builtin_amdgcn_readfirstlane(tid / WAVE), lane = tid & (WAVE - 1);
     u32 cnt = 0, na = 0;
-    u32 x[16], y[16];
-    auto load = [&](u32 (&v)[16], u32 s0) {
-        if (s0 + BT_STEP <= len) bt_load_step<false>(row, s0, len, w, lane, v);
-        else bt_load_step<true>(row, s0, len, w, lane, v);
+    u32 x[IPT], y[IPT];
+    auto load = [&](u32 (&v)[IPT], u32 s0) {
+        if (s0 + STEP <= len) bt_load_step<false, IPT>(row, s0, len, w, lane, v);
+        else bt_load_step<true, IPT>(row, s0, len, w, lane, v);
     };
-    auto step = [&](const u32 (&v)[16], u32 s0) {
-        if (s0 + BT_STEP <= len) bt_fast_step<LARGEST, false>(v, s0, len, w, lane, fL, fR, reg, cnt, na);
-        else bt_fast_step<LARGEST, true>(v, s0, len, w, lane, fL, fR, reg, cnt, na);
+    auto step = [&](const u32 (&v)[IPT], u32 s0) {
+        if (s0 + STEP <= len) bt_fast_step<LARGEST, false, IPT>(v, s0, len, w, lane, fL, fR, reg, cnt, na);
+        else bt_fast_step<LARGEST, true, IPT>(v, s0, len, w, lane, fL, fR, reg, cnt, na);
     };
     u32 s0 = 0;
     load(x, 0);
     for (;;) {
         // the next step's loads go out before this step is classified (past
         // the end: the last step again, whose addresses are valid)
-        const u32 s1 = s0 + BT_STEP < len ? s0 + BT_STEP : s0;
+        const u32 s1 = s0 + STEP < len ? s0 + STEP : s0;
         load(y, s1);
         step(x, s0);
         if (s1 == s0) break;
         s0 = s1;
-        const u32 s2 = s0 + BT_STEP < len ? s0 + BT_STEP : s0;
+        const u32 s2 = s0 + STEP < len ? s0 + STEP : s0;
         load(x, s2);
         step(y, s0);
         if (s2 == s0) break;
@@ -668,6 +690,163 @@ __device__ __forceinline__ u64 bt_reg_row(const u32 *__restrict__ row, u32 len, 
     return tau;
 }
 
+// ---- One wave per row -----------------------------------------------------
+// A row of fewer than BT_WAVE_M * 64 keys is solved by one wave alone, its
+// key order words in registers (column j * 64 + lane in o[j]): the radix
+// select and the output run on wave-level operations and the wave's own LDS,
+// with no workgroup barrier, so the four waves of a workgroup work on four
+// rows at once.
+
+// Pair of rank `rank` (0-based) among the wave's pairs (o[j], j 64 + lane),
+// valid below column n: radix select over windows of BT_BITS bits of the
+// pair from the top until the bucket holding the rank has at most 64 pairs,
+// which are ranked by comparison.  Every bin of L.hist is zero on entry and
+// on return.  Wave-uniform result.
+template <int M>
+__device__ __forceinline__ u64 bt_wave_select(const u32 (&o)[M], u32 n, u32 rank, BtWaveLds &L)
+{
+    const u32 lane = bt_tid() & (WAVE - 1);
+    const u32 jn = (n + WAVE - 1) / WAVE;
+    u32 ph = 0, pl = 0;                 // prefix: the bits at and above lowb are fixed
+    int lowb = 64;
+    u32 rk = rank, cnt = n;
+    auto match = [&](u32 oj, u32 col) -> bool {
+        if (lowb >= 64) return true;
+        if (lowb >= 32) return (oj >> (lowb - 32)) == (ph >> (lowb - 32));
+        return oj == ph && (col >> lowb) == (pl >> lowb);
+    };
+    while (cnt > (u32)WAVE && lowb > 0) {
+        const int sh_ = lowb > BT_BITS ? lowb - BT_BITS : 0;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            if ((u32)j < jn) {
+                const u32 col = (u32)j * WAVE + lane;
+                if (col < n && match(o[j], col)) {
+                    const u32 d = sh_ >= 32 ? (o[j] >> (sh_ - 32)) & (BT_BINS - 1)
+                                            : (u32)(pack(o[j], col) >> sh_) & (BT_BINS - 1);
+                    atomicAdd(&L.hist[d], 1u);
+                }
+            }
+        }
+        // lane l scans bins [16 l, 16 l + 16) and leaves them at zero
+        constexpr int BPL = (int)BT_BINS / WAVE;
+        uint4 *hp = reinterpret_cast<uint4 *>(&L.hist[lane * BPL]);
+        u32 c[BPL], csum = 0;
+#pragma unroll
+        for (int q = 0; q < BPL / 4; ++q) {
+            const uint4 v = hp[q];
+            c[4 * q] = v.x; c[4 * q + 1] = v.y; c[4 * q + 2] = v.z; c[4 * q + 3] = v.w;
+            hp[q] = make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int q = 0; q < BPL; ++q) csum += c[q];
+        const u32 incl = wave_incl_scan(csum);
+        u32 before = incl - csum;
+        const bool hit = before <= rk && rk < incl;
+        u32 bin = 0, bcnt = 0, bbefore = 0;
+#pragma unroll
+        for (int q = 0; q < BPL; ++q) {
+            if (before <= rk && rk < before + c[q]) {
+                bin = lane * BPL + (u32)q;
+                bcnt = c[q];
+                bbefore = before;
+            }
+            before += c[q];
+        }
+        const int hl = __builtin_ctzll(ballot(hit));
+        bin = (u32)__builtin_amdgcn_readlane((int)bin, hl);
+        cnt = (u32)__builtin_amdgcn_readlane((int)bcnt, hl);
+        rk -= (u32)__builtin_amdgcn_readlane((int)bbefore, hl);
+        const u64 bsel = (u64)bin << sh_;
+        ph |= (u32)(bsel >> 32);
+        pl |= (u32)bsel;
+        lowb = sh_;
+    }
+    if (lowb == 0) return ((u64)ph << 32) | pl;     // every bit fixed: that pair
+    // at most 64 candidates: compact them into L.cand (ballot order) and rank
+    u32 base = 0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        if ((u32)j < jn) {
+            const u32 col = (u32)j * WAVE + lane;
+            const bool t = col < n && match(o[j], col);
+            const u64 m = ballot(t);
+            if (t) L.cand[base + mbcnt(m)] = pack(o[j], col);
+            base += (u32)__popcll(m);
+        }
+    }
+    const u64 mine = lane < cnt ? L.cand[lane] : ~0ull;
+    const u32 mlo = (u32)mine, mhi = (u32)(mine >> 32);
+    u32 lt = 0;
+    for (u32 i = 0; i < cnt; ++i) {
+        const u64 x = ((u64)(u32)__builtin_amdgcn_readlane((int)mhi, (int)i) << 32) |
+                      (u32)__builtin_amdgcn_readlane((int)mlo, (int)i);
+        lt += x < mine ? 1u : 0u;
+    }
+    const int fl = __builtin_ctzll(ballot(lane < cnt && lt == rk));
+    return ((u64)(u32)__builtin_amdgcn_readlane((int)mhi, fl) << 32) |
+           (u32)__builtin_amdgcn_readlane((int)mlo, fl);
+}
+
+// One row by one wave: load, select, write the columns up to the pair of
+// rank k in column order (ballot compaction, no LDS), and the k-th pair.
+template <bool LARGEST, int M>
+__device__ __forceinline__ void bt_wave_row(const BtArgs &a, u32 r, const u32 *__restrict__ row, u32 len,
+                                            u32 k, BtWaveLds &L)
+{
+    const u32 lane = bt_tid() & (WAVE - 1);
+    const u32 jn = (len + WAVE - 1) / WAVE;
+    u32 o[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const u32 col = (u32)j * WAVE + lane;
+        o[j] = (u32)j < jn ? row[col < len ? col : len - 1] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < M; ++j) o[j] = key_ord<true, LARGEST>(o[j]);
+    const u64 tau = bt_wave_select<M>(o, len, k - 1, L);
+    const u32 th = (u32)(tau >> 32), tl = (u32)tau;
+    u32 *__restrict__ out = a.out_idx + a.out_off[r];
+    u32 pos = 0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        if ((u32)j < jn) {
+            const u32 col = (u32)j * WAVE + lane;
+            const bool t = col < len && (o[j] < th || (o[j] == th && col <= tl));
+            const u64 m = ballot(t);
+            if (t) {
+                const u32 q = pos + mbcnt(m);
+                if (q < k) out[q] = col;
+            }
+            pos += (u32)__popcll(m);
+        }
+    }
+    if (lane == 0) {
+        a.kth_idx[r] = tl;
+        a.kth_key[r] = row[tl];
+    }
+}
+
+// A row of the wave mode (its class is at most BT_WAVE_CLS).
+template <bool LARGEST>
+__device__ __forceinline__ void bt_wave_dispatch(const BtArgs &a, u32 r, BtWaveLds &L)
+{
+    const u64 off = a.row_off[r];
+    const u64 len64 = a.row_off[r + 1] - off;
+    const u32 k = a.k[r];
+    const u32 cls = len_class(len64);
+    if (cls < a.cls_lo || cls > a.cls_hi) return;
+    if (k == 0 || (u64)k > len64) {
+        if ((bt_tid() & (WAVE - 1)) == 0) atomicOr(a.status, (u32)TOPK_STATUS_BAD_ROW);
+        return;
+    }
+    const u32 len = (u32)len64;
+    const u32 *__restrict__ row = a.keys + off;
+    if (len <= 16 * WAVE) bt_wave_row<LARGEST, 16>(a, r, row, len, k, L);
+    else if (len <= 32 * WAVE) bt_wave_row<LARGEST, 32>(a, r, row, len, k, L);
+    else bt_wave_row<LARGEST, BT_WAVE_M>(a, r, row, len, k, L);
+}
+
 template <bool LARGEST>
 __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
 {
@@ -743,8 +922,12 @@ __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
                 lds_sync();
                 u32 cw, aw;
                 u64 *reg = sh.buf + wv * BT_REG;
-                bt_fast_sweep<LARGEST>(row, len, hl ? ord_value<LARGEST>(oL) : 0.0f,
-                                       ord_value<LARGEST>(oR), hl, reg, cw, aw);
+                if (a.t_cls[cls] == 8)
+                    bt_fast_sweep<LARGEST, 8>(row, len, hl ? ord_value<LARGEST>(oL) : 0.0f,
+                                              ord_value<LARGEST>(oR), hl, reg, cw, aw);
+                else
+                    bt_fast_sweep<LARGEST, 16>(row, len, hl ? ord_value<LARGEST>(oL) : 0.0f,
+                                               ord_value<LARGEST>(oR), hl, reg, cw, aw);
                 // the wave's own region to (ord, column) pairs, in place
                 for (u32 i = ln; i < cw && i < BT_REG; i += WAVE) {
                     const u64 e = reg[i];
@@ -892,17 +1075,59 @@ __global__ __launch_bounds__(BT_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
     __shared__ BtShared sh;
     for (u32 i = threadIdx.x; i < BT_BINS; i += BT_THREADS) sh.hist[i] = 0u;
     lds_sync();
-    // rows in longest-first order from a queue: one row per grab for the first
-    // BT_Q1 positions (the long rows), then BT_QCHUNK rows per grab
-    for (;;) {
-        if (threadIdx.x == 0) sh.next = atomicAdd(a.queue, 1u);
-        lds_sync();
-        const u32 g = __builtin_amdgcn_readfirstlane(sh.next);
-        lds_sync();
-        const u32 p0 = g < BT_Q1 ? g : BT_Q1 + (g - BT_Q1) * BT_QCHUNK;
-        if (p0 >= a.rows) break;
-        const u32 p1 = g < BT_Q1 ? p0 + 1 : (p0 + BT_QCHUNK < a.rows ? p0 + BT_QCHUNK : a.rows);
-        for (u32 p = p0; p < p1; ++p) bt_row<LARGEST>(a, a.order[p], sh);
+    // order positions [0, n_wg): the rows longer than the wave mode's
+    if (threadIdx.x == 0) {
+        u32 nw = 0;
+        for (u32 c = BT_WAVE_CLS + 1; c < (u32)BT_NCLS; ++c) nw += a.cls_cnt[c];
+        sh.n_wg = nw;
+    }
+    lds_sync();
+    const u32 n_wg = __builtin_amdgcn_readfirstlane(sh.n_wg);
+    // Workgroup mode: those rows, longest first, from BT_NQ queues, one per
+    // XCD (workgroup b is dispatched to XCD b % BT_NQ): queue x hands out the
+    // positions x, x + BT_NQ, ... of [0, n_wg), one per grab for the first
+    // BT_Q1 of them (the long rows), then BT_QCHUNK per grab.  A grab is a
+    // global atomic on the queue's own counter; atomics on one address are
+    // serialised, so the workgroups of an XCD use only their own queue (a
+    // grid smaller than BT_NQ serves every queue: x = b, b + grid, ...).
+    const u32 q_first = blockIdx.x % BT_NQ;
+    const u32 q_step = gridDim.x < BT_NQ ? gridDim.x : BT_NQ;
+    for (u32 x = q_first; x < BT_NQ; x += q_step) {
+        const u32 nx = n_wg > x ? (n_wg - x + BT_NQ - 1) / BT_NQ : 0u;
+        u32 *qc = a.queue + x * BT_QSTRIDE;
+        while (nx) {
+            if (threadIdx.x == 0) sh.next = atomicAdd(qc, 1u);
+            lds_sync();
+            const u32 g = __builtin_amdgcn_readfirstlane(sh.next);
+            lds_sync();
+            const u32 q0 = g < BT_Q1 ? g : BT_Q1 + (g - BT_Q1) * BT_QCHUNK;
+            if (q0 >= nx) break;
+            const u32 q1 = g < BT_Q1 ? q0 + 1 : (q0 + BT_QCHUNK < nx ? q0 + BT_QCHUNK : nx);
+            for (u32 q = q0; q < q1; ++q) bt_row<LARGEST>(a, a.order[q * BT_NQ + x], sh);
+        }
+    }
+    // Wave mode: positions [n_wg, rows), one row per wave, BT_WQCHUNK rows
+    // per grab from the second set of queues (the same queue choice).  No
+    // workgroup barrier follows: the waves leave independently.
+    const u32 lane = bt_tid() & (WAVE - 1);
+    const u32 w = __builtin_amdgcn_readfirstlane(bt_tid() / WAVE);
+    BtWaveLds &L = reinterpret_cast<BtWaveLds *>(sh.buf)[w];
+    {
+        uint4 *hp = reinterpret_cast<uint4 *>(L.hist);
+        for (u32 i = lane; i < BT_BINS / 4; i += WAVE) hp[i] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    const u32 n_wv = a.rows - n_wg;
+    for (u32 x = q_first; x < BT_NQ; x += q_step) {
+        const u32 nx = n_wv > x ? (n_wv - x + BT_NQ - 1) / BT_NQ : 0u;
+        u32 *qc = a.queue + (BT_NQ + x) * BT_QSTRIDE;
+        while (nx) {
+            u32 g = 0;
+            if (lane == 0) g = atomicAdd(qc, BT_WQCHUNK);
+            g = __builtin_amdgcn_readfirstlane(g);
+            if (g >= nx) break;
+            const u32 g1 = g + BT_WQCHUNK < nx ? g + BT_WQCHUNK : nx;
+            for (u32 q = g; q < g1; ++q) bt_wave_dispatch<LARGEST>(a, a.order[n_wg + q * BT_NQ + x], L);
+        }
     }
 }
 
@@ -915,10 +1140,8 @@ __global__ void k_bt_init(BtArgs a)
         a.cls_cnt[t] = 0u;
         a.cls_fill[t] = 0u;
     }
-    if (t == 0) {
-        *a.status = 0u;
-        *a.queue = 0u;
-    }
+    if (t < 2 * BT_NQ) a.queue[t * BT_QSTRIDE] = 0u;
+    if (t == 0) *a.status = 0u;
 }
 
 // Rows per length class (workgroup histogram, one global add per class).
@@ -979,7 +1202,7 @@ BtLayout bt_layout(uint32_t rows)
     L.fill = off;
     off = bt_align(off + BT_NCLS * sizeof(uint32_t));
     L.queue = off;
-    off = bt_align(off + 128);
+    off = bt_align(off + (size_t)2 * BT_NQ * BT_QSTRIDE * sizeof(uint32_t));
     L.order = off;
     off = bt_align(off + (size_t)rows * sizeof(uint32_t));
     L.total = off;
@@ -991,7 +1214,8 @@ BtLayout bt_layout(uint32_t rows)
 // rows, in a file-scope device array that every call on a device shares.
 constexpr uint32_t BT_NOALLOC_MAX_ROWS = 1u << 20;
 constexpr size_t BT_NOALLOC_BYTES =
-    3 * BT_ALIGN + (((size_t)BT_NOALLOC_MAX_ROWS * sizeof(uint32_t) + BT_ALIGN - 1) / BT_ALIGN) * BT_ALIGN;
+    2 * BT_ALIGN + (size_t)2 * BT_NQ * BT_QSTRIDE * sizeof(uint32_t) +
+    (((size_t)BT_NOALLOC_MAX_ROWS * sizeof(uint32_t) + BT_ALIGN - 1) / BT_ALIGN) * BT_ALIGN;
 
 }  // namespace
 
@@ -1023,7 +1247,8 @@ hipError_t bt_enqueue(const BtArgs &a, int grid, hipStream_t s)
 // topk_create; makes `device` current while it runs and restores the caller's.
 int topk_bt_scratch_setup(int device)
 {
-    static_assert(BT_NOALLOC_BYTES >= 3 * BT_ALIGN + BT_NOALLOC_MAX_ROWS * sizeof(uint32_t),
+    static_assert(BT_NOALLOC_BYTES >= 2 * BT_ALIGN + 2 * BT_NQ * BT_QSTRIDE * sizeof(uint32_t) +
+                                          BT_NOALLOC_MAX_ROWS * sizeof(uint32_t),
                   "scratch holds the workspace layout of the largest batch");
     if (device < 0 || device >= BT_MAX_DEVICES) return TOPK_E_INVALID;
     std::lock_guard<std::mutex> lock(g_scratch_mu);
@@ -1089,6 +1314,7 @@ int bt_args(const topk_ctx *c, const float *keys, const uint64_t *row_off, uint3
     for (int i = 0; i < BT_NCLS; ++i) {
         a.s_cls[i] = (u32)(c->bt_s_cls[i] >= 0 ? c->bt_s_cls[i] : c->bt_s_target);
         a.c_cls[i] = (u32)(c->bt_c_cls[i] >= 0 ? c->bt_c_cls[i] : c->bt_c_num);
+        a.t_cls[i] = (u32)(c->bt_t_cls[i] >= 0 ? c->bt_t_cls[i] : c->bt_tile);
     }
     return TOPK_OK;
 }
@@ -1107,7 +1333,8 @@ int bt_run(topk_ctx *c, const BtArgs &a, bool graph, hipStream_t stream)
         (uint64_t)(uintptr_t)a.kth_idx, (uint64_t)(uintptr_t)a.status,
         (uint64_t)(uintptr_t)a.order, a.seed, a.attempts, a.fast, a.cls_lo, a.cls_hi,
         (uint64_t)grid};
-    for (int i = 0; i < BT_NCLS; ++i) key.push_back(((uint64_t)a.s_cls[i] << 32) | a.c_cls[i]);
+    for (int i = 0; i < BT_NCLS; ++i)
+        key.push_back(((uint64_t)a.s_cls[i] << 32) | ((uint64_t)a.t_cls[i] << 24) | a.c_cls[i]);
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
         if (!c->capture_stream &&
@@ -1215,6 +1442,36 @@ extern "C" int topk_tune_batched_f32(topk_ctx *c, const float *keys, const uint6
         c->bt_c_cls[cls] = bc;
         a.s_cls[cls] = (u32)bs;
         a.c_cls[cls] = (u32)bc;
+        if (rc != TOPK_OK) break;
+        // then the fast sweep's tile under that pair
+        int64_t bt = a.t_cls[cls];
+        best = -1.0f;
+        for (int64_t tv : {8, 16}) {
+            BtArgs t = a;
+            t.cls_lo = t.cls_hi = cls;
+            t.t_cls[cls] = (u32)tv;
+            const float ms = bt_time(c, t, reps, stream, e0, e1);
+            if (ms < 0.0f) { rc = TOPK_E_HIP; break; }
+            if (best < 0.0f || ms < best) { best = ms; bt = tv; }
+        }
+        c->bt_t_cls[cls] = bt;
+        a.t_cls[cls] = (u32)bt;
+    }
+    // the sampling attempts before the exact fallback, over the whole batch
+    if (rc == TOPK_OK) {
+        float best = -1.0f;
+        int64_t ba = c->bt_attempts;
+        for (int64_t av : {1, 2, 4, 8}) {
+            BtArgs t = a;
+            t.attempts = (u32)av;
+            const float ms = bt_time(c, t, reps, stream, e0, e1);
+            if (ms < 0.0f) { rc = TOPK_E_HIP; break; }
+            if (best < 0.0f || ms < best) { best = ms; ba = av; }
+        }
+        if (rc == TOPK_OK) {
+            c->bt_attempts = ba;
+            a.attempts = (u32)ba;
+        }
     }
     // then the resident workgroups per CU over the whole batch
     if (rc == TOPK_OK) {

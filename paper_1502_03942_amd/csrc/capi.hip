@@ -103,7 +103,8 @@ void set_defaults(topk_ctx *c)
     c->bt_wg_per_cu = 4;
     c->bt_attempts = 4;
     c->bt_fast = 1;
-    for (int i = 0; i < TOPK_BT_NCLS; ++i) c->bt_s_cls[i] = c->bt_c_cls[i] = -1;
+    c->bt_tile = 16;
+    for (int i = 0; i < TOPK_BT_NCLS; ++i) c->bt_s_cls[i] = c->bt_c_cls[i] = c->bt_t_cls[i] = -1;
 }
 
 // The tuning parameters (what topk_save_tuning writes), in a fixed order.
@@ -114,9 +115,10 @@ const ParamRef TUNING[] = {
     {"tail_max", &topk_ctx::tail_max}, {"bt_s_target", &topk_ctx::bt_s_target},
     {"bt_c_num", &topk_ctx::bt_c_num}, {"bt_wg_per_cu", &topk_ctx::bt_wg_per_cu},
     {"bt_attempts", &topk_ctx::bt_attempts}, {"bt_fast", &topk_ctx::bt_fast},
+    {"bt_tile", &topk_ctx::bt_tile},
 };
 
-// "bt_s_target@C" / "bt_c_num@C": the override of row-length class C.
+// "bt_s_target@C" / "bt_c_num@C" / "bt_tile@C": the override of row-length class C.
 int64_t *cls_param(topk_ctx *c, const char *name)
 {
     const char *at = strchr(name, '@');
@@ -125,6 +127,7 @@ int64_t *cls_param(topk_ctx *c, const char *name)
     int64_t *arr = nullptr;
     if (len == 11 && strncmp(name, "bt_s_target", 11) == 0) arr = c->bt_s_cls;
     else if (len == 8 && strncmp(name, "bt_c_num", 8) == 0) arr = c->bt_c_cls;
+    else if (len == 7 && strncmp(name, "bt_tile", 7) == 0) arr = c->bt_t_cls;
     if (!arr || !at[1]) return nullptr;
     char *end = nullptr;
     const long cls = strtol(at + 1, &end, 10);
@@ -268,19 +271,24 @@ int topk_set_param(topk_ctx *c, const char *name, int64_t v)
         {"bt_wg_per_cu", &c->bt_wg_per_cu, 1, 8},
         {"bt_attempts", &c->bt_attempts, 1, 16},
         {"bt_fast", &c->bt_fast, 0, 1},
+        {"bt_tile", &c->bt_tile, 8, 16},
     };
     if (strcmp(name, "seed") == 0) { c->seed = (uint64_t)v; return TOPK_OK; }
     int64_t *cls = cls_param(c, name);
     if (cls) {
         // -1 removes the override; otherwise the range of the global parameter
-        const bool s = name[3] == 's';
-        if (v != -1 && (v < (s ? 64 : 4) || v > (s ? 2048 : 4096))) return TOPK_E_INVALID;
+        int64_t lo = 4, hi = 4096;
+        if (name[3] == 's') lo = 64, hi = 2048;
+        else if (name[3] == 't') lo = 8, hi = 16;
+        if (v != -1 && (v < lo || v > hi || (name[3] == 't' && v != 8 && v != 16)))
+            return TOPK_E_INVALID;
         *cls = v;
         return TOPK_OK;
     }
     for (auto &e : tab) {
         if (strcmp(name, e.n) == 0) {
             if (v < e.lo || v > e.hi) return TOPK_E_INVALID;
+            if (e.p == &c->bt_tile && v != 8 && v != 16) return TOPK_E_INVALID;
             *e.p = v;
             return TOPK_OK;
         }
@@ -299,7 +307,7 @@ int topk_get_param(const topk_ctx *c, const char *name, int64_t *v)
         {"tail_max", c->tail_max}, {"timing", c->timing},
         {"bt_s_target", c->bt_s_target}, {"bt_c_num", c->bt_c_num},
         {"bt_wg_per_cu", c->bt_wg_per_cu}, {"bt_attempts", c->bt_attempts},
-        {"bt_fast", c->bt_fast},
+        {"bt_fast", c->bt_fast}, {"bt_tile", c->bt_tile},
     };
     for (auto &e : tab) {
         if (strcmp(name, e.n) == 0) { *v = e.val; return TOPK_OK; }
@@ -451,6 +459,7 @@ int topk_save_tuning(const topk_ctx *c, const char *path)
     for (int i = 0; i < TOPK_BT_NCLS; ++i) {
         if (c->bt_s_cls[i] >= 0) { snprintf(name, sizeof name, "bt_s_target@%d", i); put(name, c->bt_s_cls[i]); }
         if (c->bt_c_cls[i] >= 0) { snprintf(name, sizeof name, "bt_c_num@%d", i); put(name, c->bt_c_cls[i]); }
+        if (c->bt_t_cls[i] >= 0) { snprintf(name, sizeof name, "bt_tile@%d", i); put(name, c->bt_t_cls[i]); }
     }
     fprintf(f, "%s\n}\n", first ? "{" : "");
     const bool ok = fclose(f) == 0;
@@ -515,6 +524,7 @@ int topk_load_tuning(topk_ctx *c, const char *path)
     for (const ParamRef &p : TUNING) t->*p.field = c->*p.field;
     memcpy(t->bt_s_cls, c->bt_s_cls, sizeof t->bt_s_cls);
     memcpy(t->bt_c_cls, c->bt_c_cls, sizeof t->bt_c_cls);
+    memcpy(t->bt_t_cls, c->bt_t_cls, sizeof t->bt_t_cls);
     t->seed = c->seed;
     t->timing = c->timing;
     int rc = TOPK_OK;
@@ -528,6 +538,7 @@ int topk_load_tuning(topk_ctx *c, const char *path)
         for (const ParamRef &p : TUNING) c->*p.field = t->*p.field;
         memcpy(c->bt_s_cls, t->bt_s_cls, sizeof c->bt_s_cls);
         memcpy(c->bt_c_cls, t->bt_c_cls, sizeof c->bt_c_cls);
+        memcpy(c->bt_t_cls, t->bt_t_cls, sizeof c->bt_t_cls);
     }
     delete t;
     return rc;

@@ -16,10 +16,11 @@ struct topk_ctx {
     uint64_t seed;
     int64_t s_target, c_num, t_fin, r_max, r_fast, band_div, tail_max, timing;
     // batched form: sample size of a long row, pivot spread, workgroups per CU,
-    // sampling attempts before the exact fallback, fast sweep on/off
-    int64_t bt_s_target, bt_c_num, bt_wg_per_cu, bt_attempts, bt_fast;
-    // per row-length class overrides of bt_s_target / bt_c_num (-1: none)
-    int64_t bt_s_cls[TOPK_BT_NCLS], bt_c_cls[TOPK_BT_NCLS];
+    // sampling attempts before the exact fallback, fast sweep on/off, fast
+    // sweep tile (keys per thread per step)
+    int64_t bt_s_target, bt_c_num, bt_wg_per_cu, bt_attempts, bt_fast, bt_tile;
+    // per row-length class overrides of bt_s_target / bt_c_num / bt_tile (-1: none)
+    int64_t bt_s_cls[TOPK_BT_NCLS], bt_c_cls[TOPK_BT_NCLS], bt_t_cls[TOPK_BT_NCLS];
     int num_cu;
     // kernel timing: event pairs recorded by calls since the last read-out
     std::vector<hipEvent_t> ev;

@@ -144,15 +144,15 @@ def test_batched_fullsize(dev):
     check_rows(keys, off, kk, res, False, full=False)
 
 
-@pytest.mark.parametrize("fast", [0, 1])
+@pytest.mark.parametrize("fast,tile", [(0, 16), (1, 16), (1, 8)])
 @pytest.mark.parametrize("largest", [False, True])
-def test_batched_fast_and_general_agree(dev, fast, largest):
-    # the same rows through the fast sweep and through the general sweep
-    rng = np.random.default_rng(40)
-    lens = [4097, 6000, 13000, 33000, 100000, 262144, 9000, 20000]
-    ks = [1, 2048, 700, 2048, 1, 1500, 9000, 20000]
+def test_batched_fast_and_general_agree(dev, fast, tile, largest):
+    # the same rows through the fast sweep (both tiles) and through the
+    # general sweep; lengths with ragged last tiles of either size
+    lens = [4097, 6000, 13000, 33000, 100000, 262144, 9000, 20000, 10241, 8193 + 2048]
+    ks = [1, 2048, 700, 2048, 1, 1500, 9000, 20000, 333, 2048]
     keys, off, kk = ragged(lens, ks, lambda n: synth.specials_f32(n, 41))
-    ctx = tk.Context(0, seed=9).set_param("bt_fast", fast)
+    ctx = tk.Context(0, seed=9).set_param("bt_fast", fast).set_param("bt_tile", tile)
     res = ctx.select_batched(*to_dev(keys, off, kk, dev), largest=largest)
     check_rows(keys, off, kk, res, largest)
 
@@ -183,9 +183,11 @@ def test_batched_fullsize_tuned_as_benched(dev):
     ctx = tk.Context(0, seed=0x5EED)
     args = to_dev(keys, off, kk, dev)
     ctx.tune_batched(*args, reps=3)
-    tuned = {c: (ctx.get_param("bt_s_target@%d" % c), ctx.get_param("bt_c_num@%d" % c))
+    tuned = {c: (ctx.get_param("bt_s_target@%d" % c), ctx.get_param("bt_c_num@%d" % c),
+                 ctx.get_param("bt_tile@%d" % c))
              for c in range(34) if ctx.get_param("bt_s_target@%d" % c) >= 0}
-    print("tuned:", tuned, "wg/cu", ctx.get_param("bt_wg_per_cu"), flush=True)
+    print("tuned:", tuned, "wg/cu", ctx.get_param("bt_wg_per_cu"),
+          "attempts", ctx.get_param("bt_attempts"), flush=True)
     res = ctx.select_batched(*args, graph=True)
     res = ctx.select_batched(*args, graph=True, out=res)
     lens = np.diff(off.astype(np.int64))

@@ -31,11 +31,13 @@ def test_tune_batched_keeps_results_exact(dev):
     present = {int(L).bit_length() for L in lens if L > 8192}
     for c in range(34):
         s, cn = ctx.get_param(f"bt_s_target@{c}"), ctx.get_param(f"bt_c_num@{c}")
+        t = ctx.get_param(f"bt_tile@{c}")
         if c in present:
-            assert s in S_CAND and cn in C_CAND, (c, s, cn)
+            assert s in S_CAND and cn in C_CAND and t in (8, 16), (c, s, cn, t)
         else:
-            assert s == -1 and cn == -1, c
+            assert s == -1 and cn == -1 and t == -1, c
     assert ctx.get_param("bt_wg_per_cu") in (2, 3, 4)
+    assert ctx.get_param("bt_attempts") in (1, 2, 4, 8)
     res = ctx.select_batched(*args)
     check_rows(keys, off, kk, res, False)
     res = ctx.select_batched(*args, largest=True)
@@ -43,7 +45,7 @@ def test_tune_batched_keeps_results_exact(dev):
 
 
 NAMES = ["s_target", "c_num", "t_fin", "r_max", "r_fast", "band_div", "tail_max",
-         "bt_s_target", "bt_c_num", "bt_wg_per_cu", "bt_attempts", "bt_fast"]
+         "bt_s_target", "bt_c_num", "bt_wg_per_cu", "bt_attempts", "bt_fast", "bt_tile"]
 
 
 def params(ctx):
@@ -51,6 +53,7 @@ def params(ctx):
     for c in range(34):
         d[f"bt_s_target@{c}"] = ctx.get_param(f"bt_s_target@{c}")
         d[f"bt_c_num@{c}"] = ctx.get_param(f"bt_c_num@{c}")
+        d[f"bt_tile@{c}"] = ctx.get_param(f"bt_tile@{c}")
     return d
 
 
@@ -58,7 +61,8 @@ def test_tuning_file_roundtrip(dev, tmp_path):
     a = tk.Context(0)
     defaults = params(a)
     a.set_param("s_target", 2048).set_param("c_num", 12).set_param("bt_s_target@15", 512)
-    a.set_param("bt_c_num@17", 16).set_param("bt_wg_per_cu", 3)
+    a.set_param("bt_c_num@17", 16).set_param("bt_wg_per_cu", 3).set_param("bt_tile@18", 8)
+    a.set_param("bt_tile", 8)
     path = tmp_path / "t.json"
     a.save_tuning(path)
     b = tk.Context(0).load_tuning(path)
@@ -80,6 +84,9 @@ def test_tuning_file_roundtrip(dev, tmp_path):
         a.set_param("bt_s_target@34", 512)
     with pytest.raises(tk.TopkError):
         a.set_param("bt_c_num@3", 2)
+    for bad_tile in (("bt_tile", 12), ("bt_tile@20", 12), ("bt_tile", 32)):
+        with pytest.raises(tk.TopkError):
+            a.set_param(*bad_tile)
 
 
 def test_tune_single_keeps_results_exact(dev):
