@@ -621,6 +621,17 @@ __global__ __launch_bounds__(PV_THREADS) void k_pivot(SelArgs a)
     sample_and_pivot<IS_F32, LARGEST>(a, st, sm);
 }
 
+// A round of the tail kernel (pivots, or the exact fallback's pivot, then the
+// workgroup-wide sweep).  Rare after the multi-workgroup rounds, so kept out
+// of line: its registers are not the finisher's (which would spill).
+template <bool IS_F32, bool LARGEST>
+__device__ __noinline__ void tail_round(const SelArgs &a, State *st, Smem &sm)
+{
+    if (sm.tag >= a.r_max) exact_pivot<IS_F32, LARGEST>(a, st, sm);
+    else sample_and_pivot<IS_F32, LARGEST>(a, st, sm);
+    block_sweep<IS_F32, LARGEST>(a, st, sm);
+}
+
 template <bool IS_F32, bool LARGEST>
 __global__ __launch_bounds__(PV_THREADS) void k_tail(SelArgs a)
 {
@@ -640,9 +651,7 @@ __global__ __launch_bounds__(PV_THREADS) void k_tail(SelArgs a)
             finish<IS_F32, LARGEST>(a, st, sm);
             return;
         }
-        if (sm.tag >= a.r_max) exact_pivot<IS_F32, LARGEST>(a, st, sm);
-        else sample_and_pivot<IS_F32, LARGEST>(a, st, sm);
-        block_sweep<IS_F32, LARGEST>(a, st, sm);
+        tail_round<IS_F32, LARGEST>(a, st, sm);
     }
 }
 
@@ -1083,9 +1092,27 @@ __device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const P
         }
         if (cb == 0) {
         } else if (cb <= (u32)SW_STASH) {
-            // b from the stash: contiguous, coalesced writes
+            // b from the stash: contiguous, coalesced writes.  The next
+            // round's sample decisions of the whole wave-tile come first, so
+            // one atomic reserves their place in the collected sample (a hot
+            // counter: one round trip per wave-tile, not per column).
+            static_assert(SW_STASH <= 32 * WAVE, "one take bit per stash column");
             const u64 pb0 = P.base_b;
-            for (u32 q0 = 0; q0 < cb; q0 += WAVE) {
+            u32 tbits = 0, ntake = 0;
+            if (hs_T) {
+                for (u32 q0 = 0, c = 0; q0 < cb; q0 += WAVE, ++c) {
+                    const u32 q = q0 + ln;
+                    const bool tk = q < cb && hash_taken(a.seed, tag + 1, (u32)P.stash[q], hs_T);
+                    tbits |= (u32)tk << c;
+                    ntake += (u32)__popcll(ballot(tk));
+                }
+            }
+            u32 sq = 0;
+            if (ntake) {
+                if (ln == 0) sq = atomicAdd(&st->hs_count, ntake);
+                sq = __builtin_amdgcn_readfirstlane(sq);
+            }
+            for (u32 q0 = 0, c = 0; q0 < cb; q0 += WAVE, ++c) {
                 const u32 q = q0 + ln;
                 const bool have = q < cb;
                 const u64 e = have ? P.stash[q] : 0ull;
@@ -1095,7 +1122,13 @@ __device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const P
                     dord[dst] = o;
                     didx[dst] = iv;
                 }
-                sample_append(a, st, have && hash_taken(a.seed, tag + 1, iv, hs_T), pack(o, iv));
+                const bool tk = (tbits >> c) & 1u;
+                const u64 mt = ballot(tk);
+                if (tk) {
+                    const u32 sp = sq + mbcnt(mt);
+                    if (sp < (u32)S_MAX) a.hs_buf[sp] = pack(o, iv);
+                }
+                sq += (u32)__popcll(mt);
             }
         } else {
             // b did not fit the stash: read the wave-tile again, one column at a time
