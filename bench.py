@@ -473,7 +473,7 @@ def bench_frequent(args):
         keys_np = gen()
         keys = torch.from_numpy(keys_np.view(np.int32)).to(dev)
         ctx = tk.Context(0, seed=0x5EED)
-        nb = int(tk.lib().topk_frequent_workspace_bytes(ctx._h, U))
+        nb = int(tk.lib().topk_frequent_workspace_bytes(ctx._h, n, U))
         ws = torch.empty(nb, dtype=torch.uint8, device=dev)
         res = {}
         for method, kstar in (("pac", 0), ("ec", k)):
@@ -505,7 +505,7 @@ def bench_frequent(args):
     kd = torch.from_numpy(keys_np.view(np.int32)).to(dev)
     vd = torch.from_numpy(vals_np.view(np.int32)).to(dev)
     ctx = tk.Context(0, seed=0x5EED)
-    ws = torch.empty(int(tk.lib().topk_sum_workspace_bytes(ctx._h, U)), dtype=torch.uint8, device=dev)
+    ws = torch.empty(int(tk.lib().topk_sum_workspace_bytes(ctx._h, nn, U)), dtype=torch.uint8, device=dev)
     s_size = int(tk.sample_size(tk.SAMPLE_SUM, nn, k, 0, eps, delta))
     res = {}
     for method, kstar in (("pac", 0), ("exact_sums", 4 * k)):

@@ -328,7 +328,18 @@ int topk_scatter_bwd_f32(const float *grad_out, const int64_t *indices, uint32_t
  *
  * Objects are integers in [0, U).  One device stands in for the paper's PEs,
  * so the distributed hash table of §7.1 is a count table over [0, U) in the
- * workspace, fed by per-workgroup LDS hash tables (local aggregation).
+ * workspace.  Context parameter "fq_mode" (0..3, default 0) picks how it is
+ * filled; results are the same:
+ *   direct (U <= 2^15 counting, 2^14 summing): every workgroup counts its
+ *        range with one LDS counter per object, the rows are added up;
+ *   partitioned (U <= 2^25): the (sampled) elements are split into
+ *        partitions by the low bits of the object, every partition is counted
+ *        with one LDS counter per object (no device atomic per element,
+ *        whatever the skew);
+ *   hashed: per-workgroup LDS hash tables (local aggregation) whose misses
+ *        go straight to the table.
+ * 0: the first that applies; 1: hashed; 2: partitioned where it applies,
+ * else hashed; 3: as 0.
  * "Most frequent" follows the unique order of §2 with the count as the
  * value: larger counts first, ties by ascending object.
  *
@@ -353,10 +364,11 @@ int topk_scatter_bwd_f32(const float *grad_out, const int64_t *indices, uint32_t
  *   sample_counts [U]  NULL, or receives every object's sample count
  *   n_sampled [1]  NULL, or receives the sample size
  *   status    [1]  TOPK_STATUS_OK or TOPK_STATUS_BAD_KEY
- *   workspace      >= topk_frequent_workspace_bytes(ctx, U), 256-byte aligned
+ *   workspace      >= topk_frequent_workspace_bytes(ctx, n, U), 256-byte aligned
+ *                  (partitioned counting: about 2 n bytes more)
  * Asynchronous on `stream`.  Returns TOPK_OK, TOPK_E_INVALID,
  * TOPK_E_WORKSPACE or TOPK_E_HIP. */
-size_t topk_frequent_workspace_bytes(const topk_ctx *ctx, uint32_t U);
+size_t topk_frequent_workspace_bytes(const topk_ctx *ctx, uint64_t n, uint32_t U);
 int topk_frequent_u32(topk_ctx *ctx, const uint32_t *keys, uint64_t n, uint32_t U, uint32_t k,
                       uint32_t kstar, uint64_t T, uint32_t *out_ids, uint32_t *out_counts,
                       uint32_t *sample_counts, uint64_t *n_sampled, uint32_t *status,
@@ -380,10 +392,11 @@ int topk_frequent_u32(topk_ctx *ctx, const uint32_t *keys, uint64_t n, uint32_t 
  *   out_ids [k], out_vals [k]  keys (largest first, ties: ascending key), values
  *   sums [U], samples [U]      NULL, or receive the sums by key / the samples
  *   status    [1]  TOPK_STATUS_OK, TOPK_STATUS_BAD_KEY, TOPK_STATUS_SUM_RANGE
- *   workspace      >= topk_sum_workspace_bytes(ctx, U), 256-byte aligned
+ *   workspace      >= topk_sum_workspace_bytes(ctx, n, U), 256-byte aligned
+ *                  (partitioned counting: about 6 n bytes more)
  * Asynchronous on `stream`.  Returns TOPK_OK, TOPK_E_INVALID,
  * TOPK_E_WORKSPACE or TOPK_E_HIP. */
-size_t topk_sum_workspace_bytes(const topk_ctx *ctx, uint32_t U);
+size_t topk_sum_workspace_bytes(const topk_ctx *ctx, uint64_t n, uint32_t U);
 int topk_sum_top_u32(topk_ctx *ctx, const uint32_t *keys, const uint32_t *values, uint64_t n,
                      uint32_t U, uint32_t k, uint32_t kstar, uint64_t s, uint32_t *out_ids,
                      uint64_t *out_vals, uint64_t *sums, uint32_t *samples, uint32_t *status,

@@ -85,10 +85,10 @@ def lib():
     L.topk_load_tuning.argtypes = [vp, ctypes.c_char_p]
     L.topk_rows_fwd_f32.argtypes = [vp, vp, u32, u32, u32, u32, vp, vp, vp]
     L.topk_scatter_bwd_f32.argtypes = [vp, vp, u32, u32, u32, vp, vp]
-    L.topk_frequent_workspace_bytes.argtypes = [vp, u32]
+    L.topk_frequent_workspace_bytes.argtypes = [vp, u64, u32]
     L.topk_frequent_workspace_bytes.restype = sz
     L.topk_frequent_u32.argtypes = [vp, vp, u64, u32, u32, u32, u64, vp, vp, vp, vp, vp, vp, sz, vp]
-    L.topk_sum_workspace_bytes.argtypes = [vp, u32]
+    L.topk_sum_workspace_bytes.argtypes = [vp, u64, u32]
     L.topk_sum_workspace_bytes.restype = sz
     L.topk_sum_top_u32.argtypes = [vp, vp, vp, u64, u32, u32, u32, u64, vp, vp, vp, vp, vp, vp,
                                    sz, vp]
@@ -333,7 +333,7 @@ class Context:
         dev = keys.device
         n = keys.numel()
         if workspace is None:
-            nb = int(lib().topk_frequent_workspace_bytes(self._h, U))
+            nb = int(lib().topk_frequent_workspace_bytes(self._h, n, U))
             workspace = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
         out = {"ids": torch.empty(k, dtype=torch.int32, device=dev),
                "counts": torch.empty(k, dtype=torch.int32, device=dev),
@@ -361,7 +361,7 @@ class Context:
         dev = keys.device
         n = keys.numel()
         if workspace is None:
-            nb = int(lib().topk_sum_workspace_bytes(self._h, U))
+            nb = int(lib().topk_sum_workspace_bytes(self._h, n, U))
             workspace = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
         out = {"ids": torch.empty(k, dtype=torch.int32, device=dev),
                "vals": torch.empty(k, dtype=torch.int64, device=dev),

@@ -104,6 +104,7 @@ void set_defaults(topk_ctx *c)
     c->bt_attempts = 4;
     c->bt_fast = 1;
     c->bt_tile = 16;
+    c->fq_mode = 0;
     for (int i = 0; i < TOPK_BT_NCLS; ++i) c->bt_s_cls[i] = c->bt_c_cls[i] = c->bt_t_cls[i] = -1;
 }
 
@@ -115,7 +116,7 @@ const ParamRef TUNING[] = {
     {"tail_max", &topk_ctx::tail_max}, {"bt_s_target", &topk_ctx::bt_s_target},
     {"bt_c_num", &topk_ctx::bt_c_num}, {"bt_wg_per_cu", &topk_ctx::bt_wg_per_cu},
     {"bt_attempts", &topk_ctx::bt_attempts}, {"bt_fast", &topk_ctx::bt_fast},
-    {"bt_tile", &topk_ctx::bt_tile},
+    {"bt_tile", &topk_ctx::bt_tile}, {"fq_mode", &topk_ctx::fq_mode},
 };
 
 // "bt_s_target@C" / "bt_c_num@C" / "bt_tile@C": the override of row-length class C.
@@ -272,6 +273,7 @@ int topk_set_param(topk_ctx *c, const char *name, int64_t v)
         {"bt_attempts", &c->bt_attempts, 1, 16},
         {"bt_fast", &c->bt_fast, 0, 1},
         {"bt_tile", &c->bt_tile, 8, 16},
+        {"fq_mode", &c->fq_mode, 0, 3},
     };
     if (strcmp(name, "seed") == 0) { c->seed = (uint64_t)v; return TOPK_OK; }
     int64_t *cls = cls_param(c, name);
@@ -307,7 +309,7 @@ int topk_get_param(const topk_ctx *c, const char *name, int64_t *v)
         {"tail_max", c->tail_max}, {"timing", c->timing},
         {"bt_s_target", c->bt_s_target}, {"bt_c_num", c->bt_c_num},
         {"bt_wg_per_cu", c->bt_wg_per_cu}, {"bt_attempts", c->bt_attempts},
-        {"bt_fast", c->bt_fast}, {"bt_tile", c->bt_tile},
+        {"bt_fast", c->bt_fast}, {"bt_tile", c->bt_tile}, {"fq_mode", c->fq_mode},
     };
     for (auto &e : tab) {
         if (strcmp(name, e.n) == 0) { *v = e.val; return TOPK_OK; }

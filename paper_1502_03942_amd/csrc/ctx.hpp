@@ -21,6 +21,9 @@ struct topk_ctx {
     int64_t bt_s_target, bt_c_num, bt_wg_per_cu, bt_attempts, bt_fast, bt_tile;
     // per row-length class overrides of bt_s_target / bt_c_num / bt_tile (-1: none)
     int64_t bt_s_cls[TOPK_BT_NCLS], bt_c_cls[TOPK_BT_NCLS], bt_t_cls[TOPK_BT_NCLS];
+    // most frequent objects / sum aggregation: how objects are counted (0 by
+    // the universe size, 1 LDS hash tables, 2 partitioned, 3 direct)
+    int64_t fq_mode;
     int num_cu;
     // kernel timing: event pairs recorded by calls since the last read-out
     std::vector<hipEvent_t> ev;

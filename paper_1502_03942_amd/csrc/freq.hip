@@ -3,24 +3,33 @@
 //
 // One device stands in for the paper's p PEs, so its distributed hash table
 // (which spreads objects over PEs) becomes a direct-mapped count table over
-// the object universe [0, U) in HBM; each workgroup first aggregates in an
-// LDS hash table (the local aggregation §7.4 recommends before insertion)
-// and adds its entries to the table with one atomic per object.
+// the object universe [0, U) in HBM.  Counting (and summing) by object runs
+// in one of two ways:
+//   partitioned (U <= 2^25, the default): the elements are first split into
+//        partitions by the low bits of the object, then each partition is
+//        counted in LDS with a direct counter per object (k_fa_*); no device
+//        atomic per element, whatever the skew of the stream;
+//   hashed: each workgroup aggregates in an LDS hash table (the local
+//        aggregation §7.4 recommends before insertion) and adds its entries
+//        to the table with one atomic per object; the objects that miss the
+//        table go straight to it (k_freq_count, k_sum_aggregate).
 //
-//   PAC: k_freq_count (Bernoulli sample by per-element Philox decisions,
-//        counted by object), the library's own selection of the k largest
-//        counts (§7.1 selects with the Algorithm of §2), k_freq_rank.
+//   PAC: the Bernoulli sample (per-element Philox decisions) counted by
+//        object, the library's own selection of the k largest counts (§7.1
+//        selects with the Algorithm of §2), k_freq_rank.
 //   EC:  the same, selecting k* objects, then k_freq_exact (one more sweep
 //        counting the k* candidates exactly, LDS hash set) and k_freq_rank
 //        of the candidates by exact count.
-//   Sum: k_sum_aggregate (sums by key), k_sum_sample (the weighted sample of
-//        §8), selection and ranking as PAC or EC, exact sums from the table.
+//   Sum: sums by key, k_sum_sample (the weighted sample of §8), selection
+//        and ranking as PAC or EC, exact sums from the table.
 //
 // "Most frequent" is the order of §2 with the count as the value: larger
 // counts first, ties by ascending object.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
+
+#include <type_traits>
 
 #include "common.hpp"
 #include "ctx.hpp"
@@ -38,6 +47,14 @@ constexpr int FQ_PROBES = 8;                    // then the object goes straight
 constexpr u32 FQ_KSTAR_MAX = 4096;              // candidates of EC
 constexpr u32 FQ_SET_SLOTS = 2 * FQ_KSTAR_MAX;  // LDS hash set of the candidates
 constexpr int FQ_RANK_THREADS = 1024;
+constexpr u32 FA_BITS = 13, FA_W = 1u << FA_BITS;  // objects per partition (one LDS counter each)
+constexpr u32 FA_NB_MAX = 4096;                   // partitions at most: U <= 2^25
+constexpr u32 FA_UNIT = 1u << 18;                 // elements per counting unit at most
+constexpr u32 FA_UNITS_MAX = (1u << 14) + FA_NB_MAX;   // units at most (n < 2^32)
+constexpr u32 FD_COUNT_MAX = 1u << 15;            // direct counting: U at most (counts)
+constexpr u32 FD_SUM_MAX = 1u << 14;              // direct counting: U at most (sums)
+constexpr int FD_THREADS = 1024;
+constexpr int FA_SCAN_P = 64;                     // partitions per scan workgroup
 
 struct FqArgs {
     const u32 *keys;        // objects (u32 < U)
@@ -57,7 +74,30 @@ struct FqArgs {
     u64 *out_vals;          // sum: [k] sample counts or exact sums
     u32 *status;
     u64 s_target;           // sum aggregation: desired sample size
+    // partitioned counting
+    u32 nb_log;             // log2 of the number of partitions NB
+    u32 *whist;             // [G][NB] elements per (workgroup, partition), then offsets
+    u32 *ptot;              // [NB] partition sizes
+    u32 *pstart;            // [NB] partition starts
+    u32 *ubase;             // [NB + 1] first unit of each partition
+    u32 *unit_part;         // [FA_UNITS_MAX] partition of each unit
+    u32 *nunits;            // [1]
+    u64 *wsum;              // [G] sum aggregation: values per workgroup
+    u16 *pq;                // [n] object index within its partition
+    u32 *pv;                // [n] sum aggregation: value
+    void *partial;          // per unit (partitioned) or per workgroup (direct): counts / sums
+    u64 *wtaken;            // [G] direct counting: sampled elements per workgroup
 };
+
+// Sum of a u64 over the wave (wave-uniform): three 24-bit pieces, so no
+// piece's sum over 64 lanes can overflow 32 bits.
+__device__ __forceinline__ u64 fq_wave_sum_u64(u64 x)
+{
+    const u32 p0 = wave_sum_u32((u32)x & 0xFFFFFFu);
+    const u32 p1 = wave_sum_u32((u32)(x >> 24) & 0xFFFFFFu);
+    const u32 p2 = wave_sum_u32((u32)(x >> 48));
+    return (u64)p0 + ((u64)p1 << 24) + ((u64)p2 << 48);
+}
 
 __device__ __forceinline__ u32 fq_hash(u32 key, u32 bits)
 {
@@ -251,6 +291,470 @@ __global__ __launch_bounds__(FQ_THREADS) void k_freq_exact(FqArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Partitioned counting (and summing) by object.  Partition p of NB (a power
+// of two) holds the objects x with x mod NB = p; within it, object x is
+// x / NB < FA_W.  Splitting by the low bits puts the most frequent objects of
+// a skewed stream (which may well be neighbours) into different partitions.
+//   k_fa_hist     per workgroup of the counting grid, the sampled elements
+//                 of its range by partition (whist[wg][p]); sums: the
+//                 workgroup's total of the values
+//   k_fa_scan     whist[.][p] -> offsets within partition p; ptot[p]
+//   k_fa_starts   partition starts, the units (at most FA_UNIT elements of
+//                 one partition), the sample size and the total of values
+//   k_fa_scatter  the same elements (the same decisions) to their partition:
+//                 the object's index within it (u16), sums: the value
+//   k_fa_count    per unit, a direct LDS counter (sum) per object of the
+//                 partition, added to the table (one atomic per object and
+//                 unit; stores when the partition is one unit)
+// Elements with an object >= U are flagged and left out; sums leave out
+// values of 0 (they add nothing).
+// ---------------------------------------------------------------------------
+// The workgroup's sampled elements with an object below U (sums: and a
+// value above 0), f(object, value) each; FA_GB groups of four per thread and
+// step, every load of a step issued before the first is used.
+constexpr int FA_GB = 4;
+template <int NT, bool ALL, bool SUM, class F>
+__device__ __forceinline__ void fa_for_taken(const FqArgs &a, F f)
+{
+    u64 g0, g1;
+    fq_range(a.n, g0, g1);
+    u32 bad = 0;
+    for (u64 gs = g0 + threadIdx.x; gs < g1; gs += (u64)FA_GB * NT) {
+        u32 x[FA_GB][4], v[FA_GB][4], valid[FA_GB];
+#pragma unroll
+        for (int b = 0; b < FA_GB; ++b) {
+            const u64 g = gs + (u64)b * NT;
+            // a group past the range reads group g0 again (valid: nothing taken)
+            fq_load4(a.keys, g < g1 ? g : g0, a.n, x[b], valid[b]);
+            if (SUM) fq_load4(a.values, g < g1 ? g : g0, a.n, v[b], valid[b]);
+            if (g >= g1) valid[b] = 0u;
+        }
+#pragma unroll
+        for (int b = 0; b < FA_GB; ++b) {
+            const u64 g = gs + (u64)b * NT;
+            const u32 take = valid[b] & (ALL || !valid[b] ? 0xFu : fq_take4(g, a.seed, a.T));
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if ((take >> j) & 1u) {
+                    if (x[b][j] >= a.U) bad = 1u;
+                    else if (!SUM || v[b][j]) f(x[b][j], SUM ? v[b][j] : 1u);
+                }
+            }
+        }
+    }
+    if (ballot(bad != 0u) && lane_id() == 0) atomicOr(a.status, (u32)TOPK_STATUS_BAD_KEY);
+}
+
+template <bool ALL, bool SUM>
+__global__ __launch_bounds__(FQ_THREADS) void k_fa_hist(FqArgs a)
+{
+    __shared__ u32 hist[FA_NB_MAX];
+    __shared__ u64 wtot[FQ_THREADS / WAVE];
+    const u32 NB = 1u << a.nb_log;
+    for (u32 i = threadIdx.x; i < NB; i += FQ_THREADS) hist[i] = 0u;
+    __syncthreads();
+    u64 tot = 0;
+    fa_for_taken<FQ_THREADS, ALL, SUM>(a, [&](u32 x, u32 v) {
+        atomicAdd(&hist[x & (NB - 1)], 1u);
+        tot += v;
+    });
+    if (SUM) {
+        const u64 t = fq_wave_sum_u64(tot);
+        if (lane_id() == 0) wtot[threadIdx.x / WAVE] = t;
+    }
+    __syncthreads();
+    if (SUM && threadIdx.x == 0) {
+        u64 t = 0;
+        for (int i = 0; i < FQ_THREADS / WAVE; ++i) t += wtot[i];
+        a.wsum[blockIdx.x] = t;
+    }
+    u32 *row = a.whist + (u64)blockIdx.x * NB;
+    for (u32 p = threadIdx.x; p < NB; p += FQ_THREADS) row[p] = hist[p];
+}
+
+// Workgroup b: partitions [64 b, 64 b + 64); thread (p, segment) walks the
+// counting workgroups [seg S, seg S + S) of its partition, S = ceil(G / 16).
+__global__ __launch_bounds__(1024) void k_fa_scan(FqArgs a, u32 G)
+{
+    __shared__ u32 segsum[16][FA_SCAN_P];
+    const u32 NB = 1u << a.nb_log;
+    const u32 pl = threadIdx.x % FA_SCAN_P, seg = threadIdx.x / FA_SCAN_P;
+    const u32 p = blockIdx.x * FA_SCAN_P + pl;
+    const u32 S = (G + 15) / 16;
+    const u32 w0 = seg * S < G ? seg * S : G, w1 = w0 + S < G ? w0 + S : G;
+    u32 sum = 0;
+    if (p < NB)
+        for (u32 w = w0; w < w1; ++w) sum += a.whist[(u64)w * NB + p];
+    segsum[seg][pl] = sum;
+    __syncthreads();
+    u32 run = 0, tot = 0;
+    for (u32 i = 0; i < 16; ++i) {
+        const u32 c = segsum[i][pl];
+        run += i < seg ? c : 0u;
+        tot += c;
+    }
+    if (p < NB) {
+        for (u32 w = w0; w < w1; ++w) {
+            u32 *q = a.whist + (u64)w * NB + p;
+            const u32 c = *q;
+            *q = run;
+            run += c;
+        }
+        if (seg == 0) a.ptot[p] = tot;
+    }
+}
+
+// One workgroup of 1024 threads: thread t covers partitions [4 t, 4 t + 4).
+__global__ __launch_bounds__(1024) void k_fa_starts(FqArgs a, u32 G, u32 sum)
+{
+    __shared__ u32 scan[1024 / WAVE];
+    __shared__ u64 vt[1024 / WAVE];
+    const u32 NB = 1u << a.nb_log;
+    static_assert(FA_NB_MAX == 4 * 1024, "four partitions per thread");
+    u32 c[4], nu[4], cs = 0, us = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const u32 p = 4 * threadIdx.x + (u32)i;
+        c[i] = p < NB ? a.ptot[p] : 0u;
+        nu[i] = (c[i] + FA_UNIT - 1) / FA_UNIT;
+        cs += c[i];
+        us += nu[i];
+    }
+    u32 ctot, utot;
+    u32 cb = block_excl_scan<1024>(cs, scan, &ctot);
+    u32 ub = block_excl_scan<1024>(us, scan, &utot);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const u32 p = 4 * threadIdx.x + (u32)i;
+        if (p < NB) {
+            a.pstart[p] = cb;
+            a.ubase[p] = ub;
+            for (u32 j = 0; j < nu[i]; ++j) a.unit_part[ub + j] = p;
+        }
+        cb += c[i];
+        ub += nu[i];
+    }
+    if (threadIdx.x == 0) {
+        a.ubase[NB] = utot;
+        *a.nunits = utot;
+        if (!sum) *a.n_sampled = ctot;      // sums: the weighted sample counts it later
+    }
+    if (sum) {
+        u64 t = 0;
+        for (u32 w = threadIdx.x; w < G; w += 1024) t += a.wsum[w];
+        t = fq_wave_sum_u64(t);
+        if (lane_id() == 0) vt[threadIdx.x / WAVE] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            u64 m = 0;
+            for (int i = 0; i < 1024 / WAVE; ++i) m += vt[i];
+            *a.total = m;
+        }
+    }
+}
+
+// Pass 2 in tiles of FA_TILE elements per workgroup: every element gets its
+// rank within its partition in the tile (an LDS atomic), the tile is staged
+// in LDS in partition order, then copied out so that each partition's run
+// of the tile goes to consecutive positions (stores in runs, not scattered
+// over NB regions).
+constexpr int FA_TG = 2;                                 // groups of four per thread and tile
+constexpr u32 FA_TILE = (u32)FQ_THREADS * 4 * FA_TG;     // 4096 elements
+template <bool ALL, bool SUM>
+__global__ __launch_bounds__(FQ_THREADS) void k_fa_scatter(FqArgs a)
+{
+    __shared__ u32 cur[FA_NB_MAX];      // next position of each partition (device)
+    __shared__ u32 tcnt[FA_NB_MAX];     // tile: elements per partition, then their start
+    __shared__ u32 stage_x[FA_TILE];
+    __shared__ u32 stage_v[SUM ? FA_TILE : 1];
+    __shared__ u32 scan[FQ_THREADS / WAVE];
+    const u32 NB = 1u << a.nb_log, sh = a.nb_log, tid = threadIdx.x;
+    const u32 *row = a.whist + (u64)blockIdx.x * NB;
+    for (u32 p = tid; p < NB; p += FQ_THREADS) {
+        cur[p] = a.pstart[p] + row[p];
+        tcnt[p] = 0u;
+    }
+    __syncthreads();
+    u64 g0, g1;
+    fq_range(a.n, g0, g1);
+    u32 bad = 0;
+    constexpr int E = 4 * FA_TG;
+    const u32 per_p = (NB + FQ_THREADS - 1) / FQ_THREADS;   // partitions per thread in the scan
+    for (u64 gs = g0; gs < g1; gs += (u64)FQ_THREADS * FA_TG) {
+        // (1) the tile's elements: loads first, then decisions
+        u32 x[FA_TG][4], v[FA_TG][4], valid[FA_TG];
+#pragma unroll
+        for (int b = 0; b < FA_TG; ++b) {
+            const u64 g = gs + (u64)b * FQ_THREADS + tid;
+            fq_load4(a.keys, g < g1 ? g : g0, a.n, x[b], valid[b]);
+            if (SUM) fq_load4(a.values, g < g1 ? g : g0, a.n, v[b], valid[b]);
+            if (g >= g1) valid[b] = 0u;
+        }
+        u32 rk[E];
+        bool use[E];
+#pragma unroll
+        for (int b = 0; b < FA_TG; ++b) {
+            const u64 g = gs + (u64)b * FQ_THREADS + tid;
+            const u32 take = valid[b] & (ALL || !valid[b] ? 0xFu : fq_take4(g, a.seed, a.T));
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int e = 4 * b + j;
+                const bool t = (take >> j) & 1u;
+                if (t && x[b][j] >= a.U) bad = 1u;
+                use[e] = t && x[b][j] < a.U && (!SUM || v[b][j] != 0u);
+                // (2) rank within the partition in this tile
+                rk[e] = use[e] ? atomicAdd(&tcnt[x[b][j] & (NB - 1)], 1u) : 0u;
+            }
+        }
+        __syncthreads();
+        // (3) partition starts within the tile (exclusive scan of tcnt)
+        u32 loc = 0;
+        for (u32 i = 0; i < per_p; ++i) {
+            const u32 p = tid * per_p + i;
+            loc += p < NB ? tcnt[p] : 0u;
+        }
+        u32 ttot;
+        u32 run = block_excl_scan<FQ_THREADS, true>(loc, scan, &ttot);
+        for (u32 i = 0; i < per_p; ++i) {
+            const u32 p = tid * per_p + i;
+            if (p < NB) {
+                const u32 c = tcnt[p];
+                tcnt[p] = run;
+                run += c;
+            }
+        }
+        lds_sync();
+        // (4) stage in partition order
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (use[e]) {
+                const u32 xe = x[e / 4][e % 4];
+                const u32 at = tcnt[xe & (NB - 1)] + rk[e];
+                stage_x[at] = xe;
+                if (SUM) stage_v[at] = v[e / 4][e % 4];
+            }
+        }
+        lds_sync();
+        // (5) copy out: slot i of partition p goes to cur[p] + (i - start of p)
+        for (u32 i = tid; i < ttot; i += FQ_THREADS) {
+            const u32 xe = stage_x[i];
+            const u32 p = xe & (NB - 1);
+            const u32 pos = cur[p] + (i - tcnt[p]);
+            a.pq[pos] = (u16)(xe >> sh);
+            if (SUM) a.pv[pos] = stage_v[i];
+        }
+        lds_sync();
+        // (6) advance the cursors, clear the tile counts
+        for (u32 i = 0; i < per_p; ++i) {
+            const u32 p = tid * per_p + i;
+            if (p < NB) {
+                const u32 nxt = p + 1 < NB ? tcnt[p + 1] : ttot;
+                cur[p] += nxt - tcnt[p];
+            }
+        }
+        lds_sync();
+        for (u32 i = 0; i < per_p; ++i) {
+            const u32 p = tid * per_p + i;
+            if (p < NB) tcnt[p] = 0u;
+        }
+        lds_sync();
+    }
+    if (ballot(bad != 0u) && lane_id() == 0) atomicOr(a.status, (u32)TOPK_STATUS_BAD_KEY);
+}
+
+// Count the lanes in `act` into LDS counter q (sums: add v into it).  The
+// lanes holding the same object as the wave's first active lane are merged
+// into one atomic when there are several (a skewed stream puts most of a
+// wave on a few objects, whose LDS atomics would serialise); the rest add
+// one by one.
+__device__ __forceinline__ void fa_lds_count(u32 *cnt, u32 q, bool act)
+{
+    const u64 am = ballot(act);
+    if (!am) return;
+    const int l0 = __builtin_ctzll(am);
+    const u32 q0 = (u32)__builtin_amdgcn_readlane((int)q, l0);
+    const bool same = act && q == q0;
+    const u64 sm = ballot(same);
+    if (__popcll(sm) > 1) {
+        if ((int)lane_id() == l0) atomicAdd(&cnt[q0], (u32)__popcll(sm));
+        act = act && !same;
+    }
+    if (act) atomicAdd(&cnt[q], 1u);
+}
+
+__device__ __forceinline__ void fa_lds_sum(unsigned long long *cnt, u32 q, u32 v, bool act)
+{
+    const u64 am = ballot(act);
+    if (!am) return;
+    const int l0 = __builtin_ctzll(am);
+    const u32 q0 = (u32)__builtin_amdgcn_readlane((int)q, l0);
+    const bool same = act && q == q0;
+    const u64 sm = ballot(same);
+    if (__popcll(sm) > 1) {
+        // the group's values in two 16-bit halves (each wave sum < 2^22)
+        const u32 lo = wave_sum_u32(same ? (v & 0xFFFFu) : 0u);
+        const u32 hi = wave_sum_u32(same ? (v >> 16) : 0u);
+        if ((int)lane_id() == l0) atomicAdd(&cnt[q0], ((unsigned long long)hi << 16) + lo);
+        act = act && !same;
+    }
+    if (act) atomicAdd(&cnt[q], (unsigned long long)v);
+}
+
+template <bool SUM>
+__global__ __launch_bounds__(FQ_THREADS) void k_fa_count(FqArgs a)
+{
+    __shared__ unsigned long long lds[SUM ? FA_W : FA_W / 2];
+    u32 *cnt = reinterpret_cast<u32 *>(lds);
+    unsigned long long *sums = lds;
+    const u32 nu = *a.nunits, sh = a.nb_log;
+    for (u32 u = blockIdx.x; u < nu; u += gridDim.x) {
+        const u32 p = a.unit_part[u];
+        const u32 tot = a.ptot[p];
+        const u32 c0 = (u - a.ubase[p]) * FA_UNIT;
+        const u32 s0 = a.pstart[p] + c0;
+        const u32 s1 = a.pstart[p] + (tot - c0 < FA_UNIT ? tot : c0 + FA_UNIT);
+        const bool single = tot <= FA_UNIT;
+        for (u32 i = threadIdx.x; i < FA_W; i += FQ_THREADS) {
+            if (SUM) sums[i] = 0ull;
+            else cnt[i] = 0u;
+        }
+        __syncthreads();
+        // the wave's elements in 64-element columns, FA_CB columns per step
+        // (uniform trip count; all loads of a step before the first use)
+        constexpr int FA_CB = 16;
+        const u32 wv = threadIdx.x / WAVE, ln = lane_id();
+        for (u32 b = s0 + wv * WAVE * FA_CB; b < s1; b += FQ_THREADS * FA_CB) {
+            u32 q[FA_CB], v[FA_CB];
+#pragma unroll
+            for (int j = 0; j < FA_CB; ++j) {
+                const u32 i = b + (u32)j * WAVE + ln;
+                q[j] = i < s1 ? (u32)a.pq[i] : 0u;
+                if (SUM) v[j] = i < s1 ? a.pv[i] : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < FA_CB; ++j) {
+                const bool act = b + (u32)j * WAVE + ln < s1;
+                if (SUM) fa_lds_sum(sums, q[j], v[j], act);
+                else fa_lds_count(cnt, q[j], act);
+            }
+        }
+        __syncthreads();
+        // the unit's counters (sums) to its row of partials: coalesced, no atomics
+        if (SUM) {
+            u64 *row = (u64 *)a.partial + (u64)u * FA_W;
+            for (u32 i = threadIdx.x; i < FA_W; i += FQ_THREADS) row[i] = sums[i];
+        } else {
+            u32 *row = (u32 *)a.partial + (u64)u * FA_W;
+            for (u32 i = threadIdx.x; i < FA_W; i += FQ_THREADS) row[i] = cnt[i];
+        }
+        __syncthreads();
+    }
+}
+
+// counts[x] (sums[x]) of partition p = x mod NB: the sum of its units' rows
+// at x / NB.  Workgroup (p, c) covers q in [256 c, 256 c + 256).
+template <bool SUM>
+__global__ __launch_bounds__(256) void k_fa_reduce(FqArgs a)
+{
+    const u32 NB = 1u << a.nb_log, per = FA_W / 256;
+    const u32 p = blockIdx.x / per, q = (blockIdx.x % per) * 256 + threadIdx.x;
+    const u32 x = (q << a.nb_log) | p;
+    if (p >= NB || x >= a.U) return;
+    const u32 u0 = a.ubase[p], u1 = a.ubase[p + 1];
+    if (SUM) {
+        u64 t = 0;
+        for (u32 u = u0; u < u1; ++u) t += ((const u64 *)a.partial)[(u64)u * FA_W + q];
+        a.sums[x] = t;
+    } else {
+        u32 t = 0;
+        for (u32 u = u0; u < u1; ++u) t += ((const u32 *)a.partial)[(u64)u * FA_W + q];
+        a.counts[x] = t;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Direct counting for small universes (U <= FD_COUNT_MAX counts, FD_SUM_MAX
+// sums): every workgroup counts its range into one LDS counter per object
+// and writes them as its row of partials; k_fd_reduce adds the rows.  One
+// pass over the input, no device atomics.
+// ---------------------------------------------------------------------------
+template <bool ALL, bool SUM>
+__global__ __launch_bounds__(FD_THREADS) void k_fd_count(FqArgs a)
+{
+    __shared__ unsigned long long lds[FD_COUNT_MAX / 2];
+    __shared__ u64 wred[FD_THREADS / WAVE];
+    static_assert(FD_SUM_MAX * 8 <= FD_COUNT_MAX * 4, "LDS holds either table");
+    u32 *cnt = reinterpret_cast<u32 *>(lds);
+    unsigned long long *sums = lds;
+    for (u32 i = threadIdx.x; i < a.U; i += FD_THREADS) {
+        if (SUM) sums[i] = 0ull;
+        else cnt[i] = 0u;
+    }
+    __syncthreads();
+    u64 tot = 0;
+    // one LDS atomic per element
+    fa_for_taken<FD_THREADS, ALL, SUM>(a, [&](u32 x, u32 v) {
+        if (SUM) atomicAdd(&sums[x], (unsigned long long)v);
+        else atomicAdd(&cnt[x], 1u);
+        tot += SUM ? v : 1u;
+    });
+    const u64 wt = fq_wave_sum_u64(tot);
+    if (lane_id() == 0) wred[threadIdx.x / WAVE] = wt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u64 t = 0;
+        for (int i = 0; i < FD_THREADS / WAVE; ++i) t += wred[i];
+        if (SUM) a.wsum[blockIdx.x] = t;
+        else a.wtaken[blockIdx.x] = t;
+    }
+    if (SUM) {
+        u64 *row = (u64 *)a.partial + (u64)blockIdx.x * a.U;
+        for (u32 i = threadIdx.x; i < a.U; i += FD_THREADS) row[i] = sums[i];
+    } else {
+        u32 *row = (u32 *)a.partial + (u64)blockIdx.x * a.U;
+        for (u32 i = threadIdx.x; i < a.U; i += FD_THREADS) row[i] = cnt[i];
+    }
+}
+
+// Column x of the partials: workgroup (64 columns) x (4 row segments), each
+// thread adds a segment with eight loads in flight, LDS adds the segments.
+template <bool SUM>
+__global__ __launch_bounds__(256) void k_fd_reduce(FqArgs a, u32 G)
+{
+    using V = typename std::conditional<SUM, u64, u32>::type;
+    __shared__ V part[4][64];
+    const u32 c = threadIdx.x % 64, sgm = threadIdx.x / 64;
+    const u32 x = blockIdx.x * 64 + c;
+    const u32 r0 = sgm * ((G + 3) / 4), r1 = r0 + (G + 3) / 4 < G ? r0 + (G + 3) / 4 : G;
+    const V *P = (const V *)a.partial;
+    V t = 0;
+    if (x < a.U) {
+        u32 w = r0;
+        for (; w + 8 <= r1; w += 8) {
+            V q[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) q[i] = P[(u64)(w + i) * a.U + x];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) t += q[i];
+        }
+        for (; w < r1; ++w) t += P[(u64)w * a.U + x];
+    }
+    part[sgm][c] = t;
+    __syncthreads();
+    if (sgm == 0 && x < a.U) {
+        const V s4 = part[0][c] + part[1][c] + part[2][c] + part[3][c];
+        if (SUM) a.sums[x] = s4;
+        else a.counts[x] = (u32)s4;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        u64 tt = 0;
+        for (u32 w = 0; w < G; ++w) tt += SUM ? a.wsum[w] : a.wtaken[w];
+        if (SUM) *a.total = tt;
+        else *a.n_sampled = tt;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Final ranking of m candidates by (value descending, object ascending); the
 // first k are written in that order.  One workgroup: each candidate's rank is
 // the number of candidates before it (m <= FQ_KSTAR_MAX).
@@ -316,8 +820,8 @@ __global__ __launch_bounds__(FQ_THREADS) void k_sum_aggregate(FqArgs a)
         }
     }
     // the total of all values (v_avg = total / s)
-    const u32 lo = wave_sum_u32((u32)tot), hi = wave_sum_u32((u32)(tot >> 32));
-    if (lane_id() == 0) atomicAdd((unsigned long long *)a.total, ((unsigned long long)hi << 32) + lo);
+    const u64 wt = fq_wave_sum_u64(tot);
+    if (lane_id() == 0) atomicAdd((unsigned long long *)a.total, (unsigned long long)wt);
     if (ballot(bad != 0u) && lane_id() == 0) atomicOr(a.status, (u32)TOPK_STATUS_BAD_KEY);
     __syncthreads();
     fq_table_flush(t, (unsigned long long *)a.sums);
@@ -391,12 +895,40 @@ namespace {
 constexpr size_t FQ_ALIGN = 256;
 inline size_t fq_align(size_t x) { return (x + FQ_ALIGN - 1) / FQ_ALIGN * FQ_ALIGN; }
 
+int fq_grid(const topk_ctx *c) { return c->num_cu * 4; }
+
+// How the table is filled: context parameter "fq_mode" 0 picks by U (direct
+// counting for small universes, partitioned up to FA_NB_MAX partitions, else
+// hashed); 1 hashed; 2 partitioned (hashed beyond it); 3 direct (else as 0).
+enum FqMethod { FQ_HASHED, FQ_PARTITIONED, FQ_DIRECT };
+FqMethod fq_method(const topk_ctx *c, uint32_t U, bool sum)
+{
+    const bool direct_ok = U <= (sum ? FD_SUM_MAX : FD_COUNT_MAX);
+    const bool part_ok = (uint64_t)U <= (uint64_t)FA_NB_MAX * FA_W;
+    switch (c->fq_mode) {
+    case 1: return FQ_HASHED;
+    case 2: return part_ok ? FQ_PARTITIONED : FQ_HASHED;
+    default: return direct_ok ? FQ_DIRECT : part_ok ? FQ_PARTITIONED : FQ_HASHED;
+    }
+}
+
+int fq_nb_log(uint32_t U)
+{
+    const uint32_t need = (U + FA_W - 1) / FA_W;
+    int l = 0;
+    while ((1u << l) < need) ++l;
+    return l;
+}
+
 struct FqLayout {
     size_t counts, sums, scal, cand, exact, sel, total;
     size_t sel_bytes;
+    FqMethod method;
+    int nb_log;
+    size_t whist, ptot, pstart, ubase, unit_part, wsum, wtaken, pq, pv, partial;
 };
 
-FqLayout fq_layout(const topk_ctx *c, uint32_t U, bool sum)
+FqLayout fq_layout(const topk_ctx *c, uint64_t n, uint32_t U, bool sum)
 {
     FqLayout L{};
     size_t off = 0;
@@ -404,8 +936,42 @@ FqLayout fq_layout(const topk_ctx *c, uint32_t U, bool sum)
     off = fq_align(off + (size_t)U * sizeof(uint32_t));
     L.sums = off;
     if (sum) off = fq_align(off + (size_t)U * sizeof(uint64_t));
-    L.scal = off;                   // n_sampled, total, kth key, kth idx
+    L.scal = off;                   // n_sampled, total, kth key, kth idx, units
     off = fq_align(off + 64);
+    L.method = fq_method(c, U, sum);
+    L.nb_log = L.method == FQ_PARTITIONED ? fq_nb_log(U) : -1;
+    const size_t vb = sum ? sizeof(uint64_t) : sizeof(uint32_t);
+    if (L.method == FQ_DIRECT) {
+        const size_t G = (size_t)c->num_cu;
+        L.wsum = off;
+        off = fq_align(off + G * sizeof(uint64_t));
+        L.wtaken = off;
+        off = fq_align(off + G * sizeof(uint64_t));
+        L.partial = off;
+        off = fq_align(off + G * (size_t)U * vb);
+    }
+    if (L.method == FQ_PARTITIONED) {
+        const size_t NB = (size_t)1 << L.nb_log, G = (size_t)fq_grid(c);
+        L.whist = off;
+        off = fq_align(off + G * NB * sizeof(uint32_t));
+        L.ptot = off;
+        off = fq_align(off + NB * sizeof(uint32_t));
+        L.pstart = off;
+        off = fq_align(off + NB * sizeof(uint32_t));
+        L.ubase = off;
+        off = fq_align(off + (NB + 1) * sizeof(uint32_t));
+        L.unit_part = off;
+        off = fq_align(off + FA_UNITS_MAX * sizeof(uint32_t));
+        L.wsum = off;
+        off = fq_align(off + G * sizeof(uint64_t));
+        L.pq = off;
+        off = fq_align(off + (size_t)n * sizeof(uint16_t));
+        L.pv = off;
+        if (sum) off = fq_align(off + (size_t)n * sizeof(uint32_t));
+        const size_t units = (size_t)((n + FA_UNIT - 1) / FA_UNIT) + NB;
+        L.partial = off;
+        off = fq_align(off + units * FA_W * vb);
+    }
     L.cand = off;
     off = fq_align(off + FQ_KSTAR_MAX * sizeof(uint32_t));
     L.exact = off;
@@ -417,7 +983,51 @@ FqLayout fq_layout(const topk_ctx *c, uint32_t U, bool sum)
     return L;
 }
 
-int fq_grid(const topk_ctx *c) { return c->num_cu * 4; }
+// Point the partitioned-counting fields of `a` into the workspace.
+void fq_bind_partitioned(FqArgs &a, const FqLayout &L, char *w)
+{
+    a.nb_log = (u32)L.nb_log;
+    a.whist = (u32 *)(w + L.whist);
+    a.ptot = (u32 *)(w + L.ptot);
+    a.pstart = (u32 *)(w + L.pstart);
+    a.ubase = (u32 *)(w + L.ubase);
+    a.unit_part = (u32 *)(w + L.unit_part);
+    a.nunits = (u32 *)(w + L.scal + 32);
+    a.wsum = (u64 *)(w + L.wsum);
+    a.pq = (u16 *)(w + L.pq);
+    a.pv = (u32 *)(w + L.pv);
+    a.partial = w + L.partial;
+}
+
+void fq_bind_direct(FqArgs &a, const FqLayout &L, char *w)
+{
+    a.wsum = (u64 *)(w + L.wsum);
+    a.wtaken = (u64 *)(w + L.wtaken);
+    a.partial = w + L.partial;
+}
+
+template <bool ALL, bool SUM>
+void fq_count_direct(const topk_ctx *c, const FqArgs &a, hipStream_t stream)
+{
+    const int G = c->num_cu;
+    hipLaunchKernelGGL((k_fd_count<ALL, SUM>), dim3(G), dim3(FD_THREADS), 0, stream, a);
+    hipLaunchKernelGGL((k_fd_reduce<SUM>), dim3((a.U + 63) / 64), dim3(256), 0, stream, a, (u32)G);
+}
+
+// The partitioned counting of the (sampled) elements into a.counts (sums:
+// a.sums and a.total); a.counts / a.sums are clear.
+template <bool ALL, bool SUM>
+void fq_count_partitioned(const topk_ctx *c, const FqArgs &a, hipStream_t stream)
+{
+    const int G = fq_grid(c);
+    const u32 NB = 1u << a.nb_log;
+    hipLaunchKernelGGL((k_fa_hist<ALL, SUM>), dim3(G), dim3(FQ_THREADS), 0, stream, a);
+    hipLaunchKernelGGL(k_fa_scan, dim3((NB + FA_SCAN_P - 1) / FA_SCAN_P), dim3(1024), 0, stream, a, (u32)G);
+    hipLaunchKernelGGL(k_fa_starts, dim3(1), dim3(1024), 0, stream, a, (u32)G, SUM ? 1u : 0u);
+    hipLaunchKernelGGL((k_fa_scatter<ALL, SUM>), dim3(G), dim3(FQ_THREADS), 0, stream, a);
+    hipLaunchKernelGGL((k_fa_count<SUM>), dim3(c->num_cu * 4), dim3(FQ_THREADS), 0, stream, a);
+    hipLaunchKernelGGL((k_fa_reduce<SUM>), dim3(NB * (FA_W / 256)), dim3(256), 0, stream, a);
+}
 
 // Shared part of both problems: select the kk objects with the largest
 // counts[] (ties by ascending object: the selection's position rule) into
@@ -434,16 +1044,16 @@ int fq_select(topk_ctx *c, const FqArgs &a, const FqLayout &L, char *w, uint32_t
 
 extern "C" {
 
-size_t topk_frequent_workspace_bytes(const topk_ctx *ctx, uint32_t U)
+size_t topk_frequent_workspace_bytes(const topk_ctx *ctx, uint64_t n, uint32_t U)
 {
     if (!ctx) return 0;
-    return fq_layout(ctx, U, false).total;
+    return fq_layout(ctx, n, U, false).total;
 }
 
-size_t topk_sum_workspace_bytes(const topk_ctx *ctx, uint32_t U)
+size_t topk_sum_workspace_bytes(const topk_ctx *ctx, uint64_t n, uint32_t U)
 {
     if (!ctx) return 0;
-    return fq_layout(ctx, U, true).total;
+    return fq_layout(ctx, n, U, true).total;
 }
 
 int topk_frequent_u32(topk_ctx *c, const uint32_t *keys, uint64_t n, uint32_t U, uint32_t k,
@@ -458,7 +1068,7 @@ int topk_frequent_u32(topk_ctx *c, const uint32_t *keys, uint64_t n, uint32_t U,
     if (kstar != 0 && (kstar < k || kstar > U || kstar > FQ_KSTAR_MAX)) return TOPK_E_INVALID;
     if (T == 0 || T > (1ull << 32)) return TOPK_E_INVALID;
     if (((uintptr_t)keys & 15u) || ((uintptr_t)workspace & (FQ_ALIGN - 1))) return TOPK_E_INVALID;
-    const FqLayout L = fq_layout(c, U, false);
+    const FqLayout L = fq_layout(c, n, U, false);
     if (ws_bytes < L.total) return TOPK_E_WORKSPACE;
     char *w = (char *)workspace;
     FqArgs a{};
@@ -479,10 +1089,19 @@ int topk_frequent_u32(topk_ctx *c, const uint32_t *keys, uint64_t n, uint32_t U,
     if (hipSetDevice(c->device) != hipSuccess) return TOPK_E_HIP;
     const int grid = fq_grid(c);
     hipLaunchKernelGGL(k_freq_clear, dim3(grid), dim3(256), 0, stream, a);
-    if (T >= (1ull << 32))
+    if (L.method == FQ_DIRECT) {
+        fq_bind_direct(a, L, w);
+        if (T >= (1ull << 32)) fq_count_direct<true, false>(c, a, stream);
+        else fq_count_direct<false, false>(c, a, stream);
+    } else if (L.method == FQ_PARTITIONED) {
+        fq_bind_partitioned(a, L, w);
+        if (T >= (1ull << 32)) fq_count_partitioned<true, false>(c, a, stream);
+        else fq_count_partitioned<false, false>(c, a, stream);
+    } else if (T >= (1ull << 32)) {
         hipLaunchKernelGGL((k_freq_count<true>), dim3(grid), dim3(FQ_THREADS), 0, stream, a);
-    else
+    } else {
         hipLaunchKernelGGL((k_freq_count<false>), dim3(grid), dim3(FQ_THREADS), 0, stream, a);
+    }
     if (hipGetLastError() != hipSuccess) return TOPK_E_HIP;
     const uint32_t kk = kstar ? kstar : k;
     int rc = fq_select(c, a, L, w, kk, stream);
@@ -511,7 +1130,7 @@ int topk_sum_top_u32(topk_ctx *c, const uint32_t *keys, const uint32_t *values, 
     if (((uintptr_t)keys & 15u) || ((uintptr_t)values & 15u) ||
         ((uintptr_t)workspace & (FQ_ALIGN - 1)))
         return TOPK_E_INVALID;
-    const FqLayout L = fq_layout(c, U, true);
+    const FqLayout L = fq_layout(c, n, U, true);
     if (ws_bytes < L.total) return TOPK_E_WORKSPACE;
     char *w = (char *)workspace;
     FqArgs a{};
@@ -535,7 +1154,15 @@ int topk_sum_top_u32(topk_ctx *c, const uint32_t *keys, const uint32_t *values, 
     if (hipSetDevice(c->device) != hipSuccess) return TOPK_E_HIP;
     const int grid = fq_grid(c);
     hipLaunchKernelGGL(k_freq_clear, dim3(grid), dim3(256), 0, stream, a);
-    hipLaunchKernelGGL(k_sum_aggregate, dim3(grid), dim3(FQ_THREADS), 0, stream, a);
+    if (L.method == FQ_DIRECT) {
+        fq_bind_direct(a, L, w);
+        fq_count_direct<true, true>(c, a, stream);
+    } else if (L.method == FQ_PARTITIONED) {
+        fq_bind_partitioned(a, L, w);
+        fq_count_partitioned<true, true>(c, a, stream);
+    } else {
+        hipLaunchKernelGGL(k_sum_aggregate, dim3(grid), dim3(FQ_THREADS), 0, stream, a);
+    }
     hipLaunchKernelGGL(k_sum_sample, dim3(grid), dim3(256), 0, stream, a);
     if (hipGetLastError() != hipSuccess) return TOPK_E_HIP;
     const uint32_t kk = kstar ? kstar : k;

@@ -13,9 +13,9 @@ constexpr int T_FIN_MAX = PV_THREADS * FIN_ITEMS;
 constexpr int SW_THREADS = 1024;               // multi-workgroup sweep: 1 control + 15 data waves
 constexpr int SW_DW = SW_THREADS / 64 - 1;     // data waves
 constexpr int SW_COLS_IN = 64;                 // input keys per data-wave lane per tile
-constexpr int SW_COLS_BAND = 32;               // band pairs per data-wave lane per tile
+constexpr int SW_COLS_BAND = 16;               // band pairs per data-wave lane per tile
 constexpr int SW_TILE_IN = SW_DW * 64 * SW_COLS_IN;     // 61440 keys
-constexpr int SW_TILE_BAND = SW_DW * 64 * SW_COLS_BAND; // 30720 pairs
+constexpr int SW_TILE_BAND = SW_DW * 64 * SW_COLS_BAND; // 15360 pairs
 constexpr int SW_STASH = 320;                  // b pairs kept in LDS per wave-tile
 constexpr int SW_SLOTS = 3;                    // wave-tile slots per data wave (pass 2 trails by 2)
 constexpr int S_MAX = PV_THREADS * SEG_CAP;    // largest usable sample (16384)

@@ -47,11 +47,14 @@ def run_freq(ctx, keys, U, k, kstar, T, dev):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("mode", [0, 1, 2])
 @pytest.mark.parametrize("dist", sorted(DISTS))
 @pytest.mark.parametrize("method", ["pac", "ec"])
-def test_frequent_parity(dev, dist, method):
+def test_frequent_parity(dev, dist, method, mode):
+    # mode 0: by universe size (direct counting for the small universes),
+    # 1: LDS hash tables, 2: partitioned counting (same results)
     gen, U = DISTS[dist]
-    ctx = tk.Context(0, seed=1234)
+    ctx = tk.Context(0, seed=1234).set_param("fq_mode", mode)
     for n in (1, 7, 4097, (1 << 20) + 3, 1 << 22):
         keys = gen(n, n % 97 + 1)
         for k in sorted({1, min(32, U), min(U, 17)}):
@@ -71,8 +74,25 @@ def test_frequent_kstar_limits_and_small_universe(dev):
 
 
 @pytest.mark.gpu
-def test_frequent_bad_keys_are_skipped(dev):
-    ctx = tk.Context(0, seed=9)
+@pytest.mark.parametrize("mode", [0, 2])
+@pytest.mark.parametrize("U", [1, 2, 8191, 8192, 8193, 3 * 8192 + 5, 1 << 15, (1 << 15) + 1,
+                               1 << 25, (1 << 25) + 1])
+def test_frequent_partition_edges(dev, U, mode):
+    # universes at the method boundaries (the largest direct universe, one
+    # partition, a ragged last partition, the most partitions, the first
+    # universe counted by hashing)
+    ctx = tk.Context(0, seed=21).set_param("fq_mode", mode)
+    n = 200003
+    keys = (synth.uniform_u32(n, U % 89 + 3) % np.uint32(U)).astype(np.uint32)
+    keys[: n // 3] = keys[: n // 3] % np.uint32(min(U, 5))          # a few hot objects
+    for kstar, T in ((0, 1 << 32), (min(U, 64), F.threshold(n, 50000))):
+        run_freq(ctx, keys, U, min(U, 10), kstar, T, dev)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_frequent_bad_keys_are_skipped(dev, mode):
+    ctx = tk.Context(0, seed=9).set_param("fq_mode", mode)
     U = 1000
     keys = synth.zipf_u32(100000, 1.0, U + 50, 3)        # some keys >= U
     out = ctx.frequent(dev_u32(keys, dev), U, 10, T=1 << 32, tables=True)
@@ -129,11 +149,14 @@ def run_sum(ctx, keys, values, U, k, kstar, s, dev):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("mode", [0, 1, 2])
 @pytest.mark.parametrize("kstar", [0, 64])
-def test_sum_parity(dev, kstar):
-    ctx = tk.Context(0, seed=77)
+def test_sum_parity(dev, kstar, mode):
+    ctx = tk.Context(0, seed=77).set_param("fq_mode", mode)
+    # the last case: values up to 2^32 - 1, so per-wave partial sums carry
+    # past 32 bits
     for n, U, vmax in ((5, 3, 10), (4099, 500, 1000), ((1 << 20) + 1, 1 << 16, 1 << 20),
-                       (1 << 22, 1 << 20, 65535)):
+                       (1 << 22, 1 << 20, 65535), (1 << 22, 1000, 0xFFFFFFFF)):
         keys, values = synth.keyed_values(n, U, 1.1, vmax, n % 13)
         for k, s in ((1, 10), (min(U, 16), 1000), (min(U, 32), 1 << 20)):
             kk = min(U, max(kstar, k)) if kstar else 0

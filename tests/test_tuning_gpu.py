@@ -45,7 +45,7 @@ def test_tune_batched_keeps_results_exact(dev):
 
 
 NAMES = ["s_target", "c_num", "t_fin", "r_max", "r_fast", "band_div", "tail_max",
-         "bt_s_target", "bt_c_num", "bt_wg_per_cu", "bt_attempts", "bt_fast", "bt_tile"]
+         "bt_s_target", "bt_c_num", "bt_wg_per_cu", "bt_attempts", "bt_fast", "bt_tile", "fq_mode"]
 
 
 def params(ctx):
