@@ -458,8 +458,8 @@ __global__ __launch_bounds__(1024) void k_fa_starts(FqArgs a, u32 G, u32 sum)
 // in LDS in partition order, then copied out so that each partition's run
 // of the tile goes to consecutive positions (stores in runs, not scattered
 // over NB regions).
-constexpr int FA_TG = 2;                                 // groups of four per thread and tile
-constexpr u32 FA_TILE = (u32)FQ_THREADS * 4 * FA_TG;     // 4096 elements
+constexpr int FA_TG = 4;                                 // groups of four per thread and tile
+constexpr u32 FA_TILE = (u32)FQ_THREADS * 4 * FA_TG;     // 8192 elements
 template <bool ALL, bool SUM>
 __global__ __launch_bounds__(FQ_THREADS) void k_fa_scatter(FqArgs a)
 {
@@ -480,16 +480,23 @@ __global__ __launch_bounds__(FQ_THREADS) void k_fa_scatter(FqArgs a)
     u32 bad = 0;
     constexpr int E = 4 * FA_TG;
     const u32 per_p = (NB + FQ_THREADS - 1) / FQ_THREADS;   // partitions per thread in the scan
-    for (u64 gs = g0; gs < g1; gs += (u64)FQ_THREADS * FA_TG) {
-        // (1) the tile's elements: loads first, then decisions
-        u32 x[FA_TG][4], v[FA_TG][4], valid[FA_TG];
+    // (1) the tile's elements; the next tile's loads are issued before this
+    // tile is processed
+    u32 x[FA_TG][4], v[FA_TG][4], valid[FA_TG];
+    auto load_tile = [&](u64 gs, u32 (&xx)[FA_TG][4], u32 (&vv)[FA_TG][4], u32 (&ok)[FA_TG]) {
 #pragma unroll
         for (int b = 0; b < FA_TG; ++b) {
             const u64 g = gs + (u64)b * FQ_THREADS + tid;
-            fq_load4(a.keys, g < g1 ? g : g0, a.n, x[b], valid[b]);
-            if (SUM) fq_load4(a.values, g < g1 ? g : g0, a.n, v[b], valid[b]);
-            if (g >= g1) valid[b] = 0u;
+            fq_load4(a.keys, g < g1 ? g : g0, a.n, xx[b], ok[b]);
+            if (SUM) fq_load4(a.values, g < g1 ? g : g0, a.n, vv[b], ok[b]);
+            if (g >= g1) ok[b] = 0u;
         }
+    };
+    if (g0 < g1) load_tile(g0, x, v, valid);
+    for (u64 gs = g0; gs < g1; gs += (u64)FQ_THREADS * FA_TG) {
+        u32 xn[FA_TG][4], vn[FA_TG][4], validn[FA_TG];
+        const u64 gn = gs + (u64)FQ_THREADS * FA_TG;
+        if (gn < g1) load_tile(gn, xn, vn, validn);
         u32 rk[E];
         bool use[E];
 #pragma unroll
@@ -558,6 +565,17 @@ __global__ __launch_bounds__(FQ_THREADS) void k_fa_scatter(FqArgs a)
             if (p < NB) tcnt[p] = 0u;
         }
         lds_sync();
+        if (gn < g1) {
+#pragma unroll
+            for (int b = 0; b < FA_TG; ++b) {
+                valid[b] = validn[b];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    x[b][j] = xn[b][j];
+                    if (SUM) v[b][j] = vn[b][j];
+                }
+            }
+        }
     }
     if (ballot(bad != 0u) && lane_id() == 0) atomicOr(a.status, (u32)TOPK_STATUS_BAD_KEY);
 }

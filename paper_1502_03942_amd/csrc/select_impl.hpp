@@ -824,6 +824,7 @@ __device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const P
                                             u32 src, u32 tag, SwShared &sh)
 {
     constexpr int COLS = KIND == 2 ? SW_COLS_BAND : SW_COLS_IN;
+    static_assert(COLS <= 64 && (COLS <= 32 || COLS % 32 == 0), "a-bits: two 32-bit words");
     constexpr u32 WSPAN = (u32)WAVE * COLS;
     const u32 lane = lane_id();
     const u32 w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -931,7 +932,8 @@ __device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const P
     };
 
     // Pass 1 over the loaded (full) wave-tile, ties left in b: a-bits (column
-    // j in bit 31 - j % 32 of A[j / 32]), b into the stash; returns |b|.
+    // j in bit W - 1 - j % 32 of A[j / 32], W = min(COLS, 32)), b into the
+    // stash; returns |b|.
     auto pass1 = [&](WSlot &S, u32 ib, u32 &A0, u32 &A1) -> u32 {
         u32 ln = lane;
         asm volatile("" : "+v"(ln));
@@ -1037,7 +1039,11 @@ __device__ __forceinline__ void sweep_waves(const SelArgs &a, State *st, const P
             const bool fits = abase + ca <= a.k;   // else a round that misses: clip at k
             u32 *__restrict__ oi = a.out_idx + abase;
             u32 ra = 0;
-            auto abit = [&](int j) -> bool { return ((((j < 32) ? A0 : A1) >> (31 - (j & 31))) & 1u) != 0; };
+            // column j went in as bit (columns in its word - 1 - j % 32)
+            constexpr int WBITS = COLS < 32 ? COLS : 32;
+            auto abit = [&](int j) -> bool {
+                return ((((j < 32) ? A0 : A1) >> (WBITS - 1 - (j & 31))) & 1u) != 0;
+            };
             if (!wkeys) {
                 // positions only (band input: still in registers)
                 auto put = [&](auto clip_tag) {
