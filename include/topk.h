@@ -365,7 +365,7 @@ int topk_scatter_bwd_f32(const float *grad_out, const int64_t *indices, uint32_t
  *   n_sampled [1]  NULL, or receives the sample size
  *   status    [1]  TOPK_STATUS_OK or TOPK_STATUS_BAD_KEY
  *   workspace      >= topk_frequent_workspace_bytes(ctx, n, U), 256-byte aligned
- *                  (partitioned counting: about 2 n bytes more)
+ *                  (partitioned counting: about 6 n bytes more)
  * Asynchronous on `stream`.  Returns TOPK_OK, TOPK_E_INVALID,
  * TOPK_E_WORKSPACE or TOPK_E_HIP. */
 size_t topk_frequent_workspace_bytes(const topk_ctx *ctx, uint64_t n, uint32_t U);

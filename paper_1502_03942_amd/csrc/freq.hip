@@ -87,6 +87,9 @@ struct FqArgs {
     u32 *pv;                // [n] sum aggregation: value
     void *partial;          // per unit (partitioned) or per workgroup (direct): counts / sums
     u64 *wtaken;            // [G] direct counting: sampled elements per workgroup
+    u32 *samp;              // [n] partitioned counting of a sample: each workgroup's
+                            // sampled objects, from its first element's index on
+    u32 *wcount;            // [G] their number
 };
 
 // Sum of a u64 over the wave (wave-uniform): three 24-bit pieces, so no
@@ -243,54 +246,6 @@ __global__ __launch_bounds__(FQ_THREADS) void k_freq_count(FqArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// EC step 2 (§7.2): count the k* candidates exactly over the whole input.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(FQ_THREADS) void k_freq_exact(FqArgs a)
-{
-    constexpr u32 BITS = 13;
-    static_assert((1u << BITS) == FQ_SET_SLOTS, "set size");
-    __shared__ u32 skey[FQ_SET_SLOTS];
-    __shared__ u32 scnt[FQ_SET_SLOTS];
-    __shared__ u16 sidx[FQ_SET_SLOTS];
-    for (u32 i = threadIdx.x; i < FQ_SET_SLOTS; i += FQ_THREADS) {
-        skey[i] = FQ_EMPTY;
-        scnt[i] = 0u;
-    }
-    __syncthreads();
-    // the candidates (distinct objects) into the set
-    for (u32 c = threadIdx.x; c < a.kstar; c += FQ_THREADS) {
-        const u32 x = a.cand[c];
-        u32 h = fq_hash(x, BITS);
-        while (atomicCAS(&skey[h], FQ_EMPTY, x) != FQ_EMPTY) h = (h + 1) & (FQ_SET_SLOTS - 1);
-        sidx[h] = (u16)c;
-    }
-    __syncthreads();
-    u64 g0, g1;
-    fq_range(a.n, g0, g1);
-    for (u64 g = g0 + threadIdx.x; g < g1; g += FQ_THREADS) {
-        u32 x[4], valid;
-        fq_load4(a.keys, g, a.n, x, valid);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if ((valid >> j) & 1u) {
-                // load factor <= 1/2: a miss ends at an empty slot
-                u32 h = fq_hash(x[j], BITS);
-                for (;;) {
-                    const u32 kx = skey[h];
-                    if (kx == x[j]) { atomicAdd(&scnt[h], 1u); break; }
-                    if (kx == FQ_EMPTY) break;
-                    h = (h + 1) & (FQ_SET_SLOTS - 1);
-                }
-            }
-        }
-    }
-    __syncthreads();
-    for (u32 i = threadIdx.x; i < FQ_SET_SLOTS; i += FQ_THREADS)
-        if (skey[i] != FQ_EMPTY && scnt[i]) atomicAdd((unsigned long long *)&a.exact[sidx[i]],
-                                                      (unsigned long long)scnt[i]);
-}
-
-// ---------------------------------------------------------------------------
 // Partitioned counting (and summing) by object.  Partition p of NB (a power
 // of two) holds the objects x with x mod NB = p; within it, object x is
 // x / NB < FA_W.  Splitting by the low bits puts the most frequent objects of
@@ -354,10 +309,53 @@ __global__ __launch_bounds__(FQ_THREADS) void k_fa_hist(FqArgs a)
     for (u32 i = threadIdx.x; i < NB; i += FQ_THREADS) hist[i] = 0u;
     __syncthreads();
     u64 tot = 0;
-    fa_for_taken<FQ_THREADS, ALL, SUM>(a, [&](u32 x, u32 v) {
-        atomicAdd(&hist[x & (NB - 1)], 1u);
-        tot += v;
-    });
+    if (ALL) {
+        fa_for_taken<FQ_THREADS, ALL, SUM>(a, [&](u32 x, u32 v) {
+            atomicAdd(&hist[x & (NB - 1)], 1u);
+            tot += v;
+        });
+    } else {
+        // a sample: its objects are also written, compacted, to the
+        // workgroup's part of samp[] (pass 2 reads only those)
+        __shared__ u32 lcnt;
+        if (threadIdx.x == 0) lcnt = 0u;
+        __syncthreads();
+        u64 g0, g1;
+        fq_range(a.n, g0, g1);
+        u32 *dst = a.samp + 4 * g0;
+        u32 bad = 0;
+        for (u64 gb = g0; gb < g1; gb += (u64)FA_GB * FQ_THREADS) {
+            u32 x[FA_GB][4], valid[FA_GB];
+#pragma unroll
+            for (int b = 0; b < FA_GB; ++b) {
+                const u64 g = gb + (u64)b * FQ_THREADS + threadIdx.x;
+                fq_load4(a.keys, g < g1 ? g : g0, a.n, x[b], valid[b]);
+                if (g >= g1) valid[b] = 0u;
+            }
+#pragma unroll
+            for (int b = 0; b < FA_GB; ++b) {
+                const u64 g = gb + (u64)b * FQ_THREADS + threadIdx.x;
+                const u32 take = valid[b] ? valid[b] & fq_take4(g, a.seed, a.T) : 0u;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const bool tk = (take >> j) & 1u;
+                    if (tk && x[b][j] >= a.U) bad = 1u;
+                    const bool use = tk && x[b][j] < a.U;
+                    if (use) atomicAdd(&hist[x[b][j] & (NB - 1)], 1u);
+                    const u64 m = ballot(use);
+                    if (m) {
+                        u32 base = 0;
+                        if (lane_id() == 0) base = atomicAdd(&lcnt, (u32)__popcll(m));
+                        base = __builtin_amdgcn_readfirstlane(base);
+                        if (use) dst[base + mbcnt(m)] = x[b][j];
+                    }
+                }
+            }
+        }
+        if (ballot(bad != 0u) && lane_id() == 0) atomicOr(a.status, (u32)TOPK_STATUS_BAD_KEY);
+        __syncthreads();
+        if (threadIdx.x == 0) a.wcount[blockIdx.x] = lcnt;
+    }
     if (SUM) {
         const u64 t = fq_wave_sum_u64(tot);
         if (lane_id() == 0) wtot[threadIdx.x / WAVE] = t;
@@ -475,8 +473,18 @@ __global__ __launch_bounds__(FQ_THREADS) void k_fa_scatter(FqArgs a)
         tcnt[p] = 0u;
     }
     __syncthreads();
+    // the elements: a sample was compacted by pass 1 (every one taken, every
+    // object below U); else the workgroup's range of the input
     u64 g0, g1;
     fq_range(a.n, g0, g1);
+    const u32 *src = a.keys;
+    u64 nsrc = a.n;
+    if (!ALL) {
+        src = a.samp + 4 * g0;
+        nsrc = a.wcount[blockIdx.x];
+        g0 = 0;
+        g1 = (nsrc + 3) / 4;
+    }
     u32 bad = 0;
     constexpr int E = 4 * FA_TG;
     const u32 per_p = (NB + FQ_THREADS - 1) / FQ_THREADS;   // partitions per thread in the scan
@@ -487,7 +495,7 @@ __global__ __launch_bounds__(FQ_THREADS) void k_fa_scatter(FqArgs a)
 #pragma unroll
         for (int b = 0; b < FA_TG; ++b) {
             const u64 g = gs + (u64)b * FQ_THREADS + tid;
-            fq_load4(a.keys, g < g1 ? g : g0, a.n, xx[b], ok[b]);
+            fq_load4(src, g < g1 ? g : g0, nsrc, xx[b], ok[b]);
             if (SUM) fq_load4(a.values, g < g1 ? g : g0, a.n, vv[b], ok[b]);
             if (g >= g1) ok[b] = 0u;
         }
@@ -501,8 +509,7 @@ __global__ __launch_bounds__(FQ_THREADS) void k_fa_scatter(FqArgs a)
         bool use[E];
 #pragma unroll
         for (int b = 0; b < FA_TG; ++b) {
-            const u64 g = gs + (u64)b * FQ_THREADS + tid;
-            const u32 take = valid[b] & (ALL || !valid[b] ? 0xFu : fq_take4(g, a.seed, a.T));
+            const u32 take = valid[b];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int e = 4 * b + j;
@@ -578,6 +585,46 @@ __global__ __launch_bounds__(FQ_THREADS) void k_fa_scatter(FqArgs a)
         }
     }
     if (ballot(bad != 0u) && lane_id() == 0) atomicOr(a.status, (u32)TOPK_STATUS_BAD_KEY);
+}
+
+// ---------------------------------------------------------------------------
+// EC step 2 (§7.2): count the k* candidates exactly over the whole input.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(FQ_THREADS) void k_freq_exact(FqArgs a)
+{
+    constexpr u32 BITS = 13;
+    static_assert((1u << BITS) == FQ_SET_SLOTS, "set size");
+    __shared__ u32 skey[FQ_SET_SLOTS];
+    __shared__ u32 scnt[FQ_SET_SLOTS];
+    __shared__ u16 sidx[FQ_SET_SLOTS];
+    for (u32 i = threadIdx.x; i < FQ_SET_SLOTS; i += FQ_THREADS) {
+        skey[i] = FQ_EMPTY;
+        scnt[i] = 0u;
+    }
+    __syncthreads();
+    // the candidates (distinct objects) into the set
+    for (u32 c = threadIdx.x; c < a.kstar; c += FQ_THREADS) {
+        const u32 x = a.cand[c];
+        u32 h = fq_hash(x, BITS);
+        while (atomicCAS(&skey[h], FQ_EMPTY, x) != FQ_EMPTY) h = (h + 1) & (FQ_SET_SLOTS - 1);
+        sidx[h] = (u16)c;
+    }
+    __syncthreads();
+    // every element (FA_GB groups of four per thread and step, loads first);
+    // load factor <= 1/2: a miss ends at an empty slot
+    fa_for_taken<FQ_THREADS, true, false>(a, [&](u32 x, u32) {
+        u32 h = fq_hash(x, BITS);
+        for (;;) {
+            const u32 kx = skey[h];
+            if (kx == x) { atomicAdd(&scnt[h], 1u); break; }
+            if (kx == FQ_EMPTY) break;
+            h = (h + 1) & (FQ_SET_SLOTS - 1);
+        }
+    });
+    __syncthreads();
+    for (u32 i = threadIdx.x; i < FQ_SET_SLOTS; i += FQ_THREADS)
+        if (skey[i] != FQ_EMPTY && scnt[i]) atomicAdd((unsigned long long *)&a.exact[sidx[i]],
+                                                      (unsigned long long)scnt[i]);
 }
 
 // Count the lanes in `act` into LDS counter q (sums: add v into it).  The
@@ -943,7 +990,7 @@ struct FqLayout {
     size_t sel_bytes;
     FqMethod method;
     int nb_log;
-    size_t whist, ptot, pstart, ubase, unit_part, wsum, wtaken, pq, pv, partial;
+    size_t whist, ptot, pstart, ubase, unit_part, wsum, wtaken, pq, pv, partial, samp, wcount;
 };
 
 FqLayout fq_layout(const topk_ctx *c, uint64_t n, uint32_t U, bool sum)
@@ -989,6 +1036,12 @@ FqLayout fq_layout(const topk_ctx *c, uint64_t n, uint32_t U, bool sum)
         const size_t units = (size_t)((n + FA_UNIT - 1) / FA_UNIT) + NB;
         L.partial = off;
         off = fq_align(off + units * FA_W * vb);
+        if (!sum) {                 // a sample's objects, compacted per workgroup
+            L.samp = off;
+            off = fq_align(off + (size_t)n * sizeof(uint32_t));
+            L.wcount = off;
+            off = fq_align(off + G * sizeof(uint32_t));
+        }
     }
     L.cand = off;
     off = fq_align(off + FQ_KSTAR_MAX * sizeof(uint32_t));
@@ -1015,6 +1068,8 @@ void fq_bind_partitioned(FqArgs &a, const FqLayout &L, char *w)
     a.pq = (u16 *)(w + L.pq);
     a.pv = (u32 *)(w + L.pv);
     a.partial = w + L.partial;
+    a.samp = (u32 *)(w + L.samp);
+    a.wcount = (u32 *)(w + L.wcount);
 }
 
 void fq_bind_direct(FqArgs &a, const FqLayout &L, char *w)
