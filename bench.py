@@ -84,7 +84,7 @@ def bench_select(args):
         if args.tuning_prefix:
             ctxs[k].load_tuning(args.tuning_prefix + "single_k%d.json" % k)
         elif not args.no_tune:
-            ctxs[k].tune(keys, k, reps=3, workspace=ws[k])
+            ctxs[k].tune(keys, k, reps=10, workspace=ws[k])
         if args.save_tuning_prefix:
             ctxs[k].save_tuning(args.save_tuning_prefix + "single_k%d.json" % k)
         tuned[str(k)] = {"s_target": ctxs[k].get_param("s_target"),
@@ -237,14 +237,15 @@ def bench_configs(args, c2_ms_per_k):
     e1 = torch.cuda.Event(enable_timing=True)
 
     def timed(fn, reps=10):
-        t = []
+        # back-to-back calls between the events, so that the host's launch
+        # latency of each call is not counted
+        torch.cuda.synchronize()
+        e0.record()
         for _ in range(reps):
-            e0.record()
             fn()
-            e1.record()
-            torch.cuda.synchronize()
-            t.append(e0.elapsed_time(e1))
-        return float(np.median(t))
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
 
     out = {}
     # stream read: the library's plain read kernel (the first sweep's access
@@ -261,7 +262,7 @@ def bench_configs(args, c2_ms_per_k):
         gbs[name] = (1 << 30) / (timed(fn) * 1e-3) / 1e9
     read_gbs = gbs["topk_stream_read"]
     out["stream_read"] = {"how": "topk_stream_read over 2^28 f32 keys (1 GiB read once, "
-                                 "256-byte non-temporal column loads), median of 10",
+                                 "256-byte non-temporal column loads), mean of 10 back-to-back calls",
                           "gbs": round(read_gbs, 1),
                           "probes_gbs": {k: round(v, 1) for k, v in gbs.items()}}
     out["C2_frac_of_stream_read"] = {
@@ -436,20 +437,20 @@ def bench_rows(args):
 
 
 def _timed(fn, reps=10):
-    """Median of reps HIP-event-timed calls (ms) on the current stream."""
+    """Mean of reps back-to-back calls (ms) on the current stream, HIP events
+    around the batch (the host's launch latency of each call is not counted)."""
     import torch
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     for _ in range(2):
         fn()
-    t = []
+    torch.cuda.synchronize()
+    e0.record()
     for _ in range(reps):
-        e0.record()
         fn()
-        e1.record()
-        torch.cuda.synchronize()
-        t.append(e0.elapsed_time(e1))
-    return float(np.median(t))
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
 
 
 def bench_frequent(args):

@@ -175,7 +175,7 @@ int topk_kernel_times(topk_ctx *ctx, float *ms, int32_t *kind, uint32_t max, uin
 /* topk_tune_f32: the autotuner of the single-instance selection.  Same
  * arguments as topk_select_f32 without out_keys and status (flags:
  * TOPK_LARGEST only; the outputs are overwritten with valid results).  The
- * call is timed (median of `reps` calls, HIP events on `stream`) under every
+ * call is timed (mean of `reps` calls, HIP events on `stream`) under every
  * pair "s_target" in {2048, 4096, 8192} x "c_num" in {8, 12, 16, 24}, and
  * the fastest pair stays in ctx.  The workspace size does not depend on
  * either parameter.  Blocks the host until the stream is idle.  Returns
@@ -186,10 +186,11 @@ int topk_tune_f32(topk_ctx *ctx, const float *keys, uint64_t n, uint64_t k, uint
                   size_t ws_bytes, uint32_t reps, hipStream_t stream);
 
 /* topk_stream_read: a measurement helper, not part of the selection.  Reads
- * keys[0 .. n) once with the access pattern of the first sweep (wave-tiles of
- * 64 columns x 64 lanes, 256-byte non-temporal loads, one 1024-thread
- * workgroup per CU) and adds a word derived from them to *sink, so that the
- * plain stream-read bandwidth of the device can be timed beside a selection.
+ * keys[0 .. n) once with the column pattern of the first sweep (wave-tiles of
+ * 64 columns x 64 lanes, 256-byte non-temporal loads; two 512-thread
+ * workgroups per CU) and adds the sum of the key bits (mod 2^32) to *sink,
+ * one atomic per workgroup, so that the plain stream-read bandwidth of the
+ * device can be timed beside a selection.
  * keys 256-byte aligned, n a positive multiple of 4096; asynchronous on
  * `stream`.  Returns TOPK_OK, TOPK_E_INVALID or TOPK_E_HIP. */
 int topk_stream_read(topk_ctx *ctx, const uint32_t *keys, uint64_t n, uint32_t *sink,
@@ -269,7 +270,7 @@ int topk_select_batched_f32_noalloc(topk_ctx *ctx, const float *keys, const uint
  * as topk_select_batched_f32 (TOPK_GRAPH ignored; the outputs are
  * overwritten with valid results).  For every length class of the batch whose
  * rows take the sampling path (longer than 8192 keys), the batch restricted to
- * that class is timed (median of `reps` calls, HIP events on `stream`) under
+ * that class is timed (mean of `reps` calls, HIP events on `stream`) under
  * each pair bt_s_target in {256, 512, 1024, 2048} x bt_c_num in
  * {8, 12, 16, 24}; the fastest pair becomes the class's "bt_s_target@C" /
  * "bt_c_num@C", and under it the faster of "bt_tile@C" in {8, 16}.  Then

@@ -433,9 +433,12 @@ int topk_tune_f32(topk_ctx *c, const float *keys, uint64_t n, uint64_t k, uint32
                 t.push_back(ms);
             }
             if (rc != TOPK_OK) break;
-            std::sort(t.begin(), t.end());
-            const float med = t[t.size() / 2];
-            if (best < 0.0f || med < best) { best = med; bs = sv; bc = cv; }
+            // the mean, so that a pair whose rounds sometimes miss (and
+            // repeat) pays for it
+            float mean = 0.0f;
+            for (float x : t) mean += x;
+            mean /= (float)t.size();
+            if (best < 0.0f || mean < best) { best = mean; bs = sv; bc = cv; }
         }
         if (rc != TOPK_OK) break;
     }

@@ -102,6 +102,22 @@ __device__ __forceinline__ u64 fq_wave_sum_u64(u64 x)
     return (u64)p0 + ((u64)p1 << 24) + ((u64)p2 << 48);
 }
 
+// Add v of every thread of the workgroup (NT threads) to *dst with one device
+// atomic per workgroup (atomics on one word serialise across the device).
+// Called by every thread; `red` is LDS of NT / 64 words.
+template <int NT>
+__device__ __forceinline__ void fq_block_add(unsigned long long *dst, u64 v, u64 *red)
+{
+    const u64 w = fq_wave_sum_u64(v);
+    if (lane_id() == 0) red[threadIdx.x / WAVE] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u64 t = 0;
+        for (int i = 0; i < NT / WAVE; ++i) t += red[i];
+        if (t) atomicAdd(dst, (unsigned long long)t);
+    }
+}
+
 __device__ __forceinline__ u32 fq_hash(u32 key, u32 bits)
 {
     return (key * 0x9E3779B1u) >> (32 - bits);     // Fibonacci hashing
@@ -238,9 +254,9 @@ __global__ __launch_bounds__(FQ_THREADS) void k_freq_count(FqArgs a)
             }
         }
     }
-    const u32 ws = wave_sum_u32(taken);
-    if (lane_id() == 0 && ws) atomicAdd((unsigned long long *)a.n_sampled, (unsigned long long)ws);
+    __shared__ u64 red[FQ_THREADS / WAVE];
     if (ballot(bad != 0u) && lane_id() == 0) atomicOr(a.status, (u32)TOPK_STATUS_BAD_KEY);
+    fq_block_add<FQ_THREADS>((unsigned long long *)a.n_sampled, taken, red);
     __syncthreads();
     fq_table_flush(t, a.counts);
 }
@@ -885,9 +901,9 @@ __global__ __launch_bounds__(FQ_THREADS) void k_sum_aggregate(FqArgs a)
         }
     }
     // the total of all values (v_avg = total / s)
-    const u64 wt = fq_wave_sum_u64(tot);
-    if (lane_id() == 0) atomicAdd((unsigned long long *)a.total, (unsigned long long)wt);
+    __shared__ u64 red[FQ_THREADS / WAVE];
     if (ballot(bad != 0u) && lane_id() == 0) atomicOr(a.status, (u32)TOPK_STATUS_BAD_KEY);
+    fq_block_add<FQ_THREADS>((unsigned long long *)a.total, tot, red);
     __syncthreads();
     fq_table_flush(t, (unsigned long long *)a.sums);
 }
@@ -925,7 +941,8 @@ __device__ __forceinline__ u64 frac32(u64 r, u64 m)
 // floor(v / v_avg) samples plus one with probability v / v_avg - that; the
 // extra one is taken iff word 0 of Philox4x32-10 at counter (x, 0, 0, 3) is
 // below floor(r 2^32 / m), r = v s mod m.
-__global__ void k_sum_sample(FqArgs a)
+constexpr int FQ_SAMPLE_THREADS = 256;
+__global__ __launch_bounds__(FQ_SAMPLE_THREADS) void k_sum_sample(FqArgs a)
 {
     u64 m = *a.total;
     const u64 i0 = (u64)blockIdx.x * blockDim.x + threadIdx.x;
@@ -947,8 +964,8 @@ __global__ void k_sum_sample(FqArgs a)
         a.counts[x] = c;
         taken += c;
     }
-    const u32 ws = wave_sum_u32(taken);
-    if (lane_id() == 0 && ws) atomicAdd((unsigned long long *)a.n_sampled, (unsigned long long)ws);
+    __shared__ u64 red[FQ_SAMPLE_THREADS / WAVE];
+    fq_block_add<FQ_SAMPLE_THREADS>((unsigned long long *)a.n_sampled, taken, red);
 }
 
 }  // namespace topk
@@ -1236,7 +1253,7 @@ int topk_sum_top_u32(topk_ctx *c, const uint32_t *keys, const uint32_t *values, 
     } else {
         hipLaunchKernelGGL(k_sum_aggregate, dim3(grid), dim3(FQ_THREADS), 0, stream, a);
     }
-    hipLaunchKernelGGL(k_sum_sample, dim3(grid), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_sum_sample, dim3(grid), dim3(FQ_SAMPLE_THREADS), 0, stream, a);
     if (hipGetLastError() != hipSuccess) return TOPK_E_HIP;
     const uint32_t kk = kstar ? kstar : k;
     int rc = fq_select(c, a, L, w, kk, stream);

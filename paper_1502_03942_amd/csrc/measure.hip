@@ -2,8 +2,10 @@
 // the first sweep's access pattern, so that the stream-read bandwidth of the
 // device can be measured next to the selection.  A wave reads wave-tiles of
 // 4096 keys as 64 columns of 64 lanes (one 256-byte non-temporal load per
-// column), one workgroup of 16 waves per CU walks the tiles grid-stride, and
-// the keys are folded into one word so that no load can be dropped.
+// column), two workgroups of 8 waves per CU walk the tiles grid-stride (the
+// fastest arrangement of this pattern measured: 6.94 TB/s against 6.74 with
+// one workgroup of 16 waves per CU), and the keys are summed into one word
+// so that no load can be dropped.
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
@@ -12,7 +14,7 @@
 
 namespace topk {
 
-constexpr int MR_THREADS = 1024;
+constexpr int MR_THREADS = 512;
 constexpr int MR_COLS = 64;
 constexpr u32 MR_TILE = MR_COLS * WAVE;
 
@@ -31,8 +33,17 @@ __global__ __launch_bounds__(MR_THREADS) void k_stream_read(const u32 *__restric
 #pragma unroll
         for (int j = 0; j < MR_COLS; ++j) acc += x[j];
     }
+    // one device atomic per workgroup (atomics on one word serialise: one per
+    // wave would add tens of microseconds)
+    __shared__ u32 red[MR_THREADS / WAVE];
     acc = wave_sum_u32(acc);
-    if (lane == 0) atomicAdd(sink, acc);
+    if (lane == 0) red[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u32 t = 0;
+        for (u32 i = 0; i < waves; ++i) t += red[i];
+        atomicAdd(sink, t);
+    }
 }
 
 }  // namespace topk
@@ -46,7 +57,7 @@ extern "C" int topk_stream_read(topk_ctx *c, const uint32_t *keys, uint64_t n, u
     if (n / MR_TILE > 0xFFFFFFFFull) return TOPK_E_INVALID;
     if ((uintptr_t)keys & 255u || (uintptr_t)sink & 3u) return TOPK_E_INVALID;
     if (hipSetDevice(c->device) != hipSuccess) return TOPK_E_HIP;
-    hipLaunchKernelGGL(k_stream_read, dim3(c->num_cu), dim3(MR_THREADS), 0, stream, keys,
+    hipLaunchKernelGGL(k_stream_read, dim3(c->num_cu * 2), dim3(MR_THREADS), 0, stream, keys,
                        (u32)(n / MR_TILE), sink);
     return hipGetLastError() == hipSuccess ? TOPK_OK : TOPK_E_HIP;
 }
