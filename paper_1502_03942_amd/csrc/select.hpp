@@ -40,9 +40,10 @@ struct State {
     uint32_t has_l, has_r, pad1, pad2;
     uint64_t hs_T;              // rate of the sample drawn from b (T = rho 2^32)
     uint32_t hs_count, pad4, pad5, pad6;   // elements taken into that sample
-    // counters hit by every sweep workgroup, each on a cache line of its own
-    alignas(128) uint64_t resv; // sweep output reservations: |a| << 32 | |b|
-    alignas(128) uint32_t gen;  // sweep generations handed out beyond the first
+    // counters hit by every sweep workgroup, each on a 4 KiB page of its own
+    // (atomics on words close together serialise with each other)
+    alignas(4096) uint64_t resv; // sweep output reservations: |a| << 32 | |b|
+    alignas(4096) uint32_t gen;  // sweep generations handed out beyond the first
     alignas(128) RoundRec rec[R_TRACE];
 };
 
