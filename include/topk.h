@@ -234,7 +234,8 @@ int topk_stream_read(topk_ctx *ctx, const uint32_t *keys, uint64_t n, uint32_t *
  *                        out_idx, band to LDS)
  * flags: TOPK_LARGEST, TOPK_GRAPH
  * (capture the four launches into a hipGraph on first use for this exact
- * argument set and replay it afterwards; the ctx keeps the graph).  All
+ * argument set and replay it afterwards; the ctx keeps up to 32 graphs and,
+ * to make room for another, drains the device and drops one).  All
  * pointers are device pointers; asynchronous on `stream`.  Returns TOPK_OK,
  * TOPK_E_INVALID (null or misaligned pointer, rows = 0, unknown flag),
  * TOPK_E_WORKSPACE or TOPK_E_HIP. */

@@ -71,6 +71,7 @@ constexpr u32 BT_QCHUNK = 4;                    // then this many per grab
 constexpr u32 BT_WAVE_CLS = 11;                 // rows of classes <= this (< 2048 keys): one wave each
 constexpr u32 BT_WAVE_M = 32;                   // their keys per lane at most
 constexpr u32 BT_WQCHUNK = 2;                   // rows per grab of a wave
+constexpr size_t BT_GRAPHS_MAX = 32;            // instantiated graphs kept per context
 
 struct BtShared {
     u64 buf[BT_CAP];
@@ -1353,12 +1354,23 @@ int bt_run(topk_ctx *c, const BtArgs &a, bool graph, hipStream_t stream)
         const hipError_t e3 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e3 != hipSuccess) return TOPK_E_HIP;
+        if (c->graphs.size() >= BT_GRAPHS_MAX) {
+            // evict one cached graph; its launches may still run on any
+            // stream, so the device is drained first (rare: only after
+            // BT_GRAPHS_MAX distinct argument sets)
+            if (hipDeviceSynchronize() != hipSuccess) {
+                (void)hipGraphExecDestroy(ge);
+                return TOPK_E_HIP;
+            }
+            (void)hipGraphExecDestroy(c->graphs.begin()->second);
+            c->graphs.erase(c->graphs.begin());
+        }
         it = c->graphs.emplace(key, ge).first;
     }
     return hipGraphLaunch(it->second, stream) == hipSuccess ? TOPK_OK : TOPK_E_HIP;
 }
 
-// Median of `reps` timed eager calls of the batch (ms), or a negative error.
+// Mean of `reps` timed eager calls of the batch (ms), or a negative error.
 float bt_time(topk_ctx *c, const BtArgs &a, uint32_t reps, hipStream_t stream, hipEvent_t e0,
               hipEvent_t e1)
 {

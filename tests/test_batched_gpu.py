@@ -121,6 +121,23 @@ def test_batched_graph_replay(dev):
     check_rows(keys2, off, kk, out, False)
 
 
+def test_batched_graph_cache_eviction(dev):
+    # more distinct argument sets (here: seeds) than the context keeps graphs
+    # for: older graphs are dropped, every replay stays exact
+    lens = [20000, 3000, 700, 9000]
+    ks = [100, 3000, 1, 2048]
+    keys, off, kk = ragged(lens, ks, lambda n: synth.normal_f32(n, 31))
+    args = to_dev(keys, off, kk, dev)
+    ctx = tk.Context(0, seed=1)
+    for i in range(40):
+        ctx.set_param("seed", 1000 + i)
+        out = ctx.select_batched(*args, graph=True)
+        if i % 13 == 0:
+            check_rows(keys, off, kk, out, False)
+    ctx.set_param("seed", 1000)
+    check_rows(keys, off, kk, ctx.select_batched(*args, graph=True), False)
+
+
 def test_batched_bad_rows(dev):
     lens = [100, 100, 100, 0]
     ks = [10, 0, 101, 0]

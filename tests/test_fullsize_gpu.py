@@ -104,3 +104,46 @@ def test_u32_2p20_k1000(dev):
     got = res["idx"].cpu().numpy().view(np.uint32)
     assert np.array_equal(np.sort(got), np.sort(ref))
     assert int(res["kth_idx"].item()) == int(ref[-1])
+
+
+@pytest.mark.parametrize("k", [1000, (1 << 31) + 5])
+def test_positions_past_2p31(dev, k):
+    # n above 2^31: positions use all 32 bits.  Too large for the oracle's
+    # sort, so the result is checked by properties that hold at any size,
+    # computed with torch on the device (independently of the library): k
+    # distinct positions in range, every selected key at or below the k-th,
+    # fewer than k keys below it and at least k at or below it, the selected
+    # keys equal to it the lowest positions among the equal ones, and the
+    # k-th key and position consistent.
+    n = (1 << 31) + 4097
+    print("positions past 2^31: n=%d k=%d" % (n, k), flush=True)
+    g = torch.Generator(device=dev)
+    g.manual_seed(123)
+    keys = torch.rand(n, generator=g, device=dev)
+    ctx = tk.Context(0, seed=7)
+    res = ctx.select(keys, k)
+    torch.cuda.synchronize()
+    assert int(res["status"].item()) == 0
+    idx = res["idx"].to(torch.int64) & 0xFFFFFFFF
+    kth = res["kth_key"]
+    kth_idx = int(res["kth_idx"].to(torch.int64).item()) & 0xFFFFFFFF
+    assert idx.numel() == k and int(idx.max().item()) < n
+    mark = torch.zeros(n, dtype=torch.bool, device=dev)
+    mark[idx] = True
+    assert int(mark.sum().item()) == k                    # distinct
+    sel = keys[idx]
+    assert bool((sel <= kth).all().item())
+    below = int((keys < kth).sum().item())
+    # positions of the keys equal to the k-th, ascending (nonzero in chunks:
+    # one call over more than 2^31 elements is not supported)
+    chunk = 1 << 30
+    eq = torch.cat([torch.nonzero(keys[c0:c0 + chunk] == kth).flatten() + c0
+                    for c0 in range(0, n, chunk)])
+    assert below < k <= below + eq.numel()
+    need = k - below
+    sel_eq = torch.sort(torch.cat([idx[c0:c0 + chunk][sel[c0:c0 + chunk] == kth]
+                                   for c0 in range(0, k, chunk)])).values
+    assert torch.equal(sel_eq, eq[:need])                 # ties by ascending position
+    assert float(keys[kth_idx].item()) == float(kth.item()) and kth_idx == int(eq[need - 1].item())
+    del keys, mark, sel, idx, res
+    torch.cuda.empty_cache()
