@@ -68,8 +68,10 @@ constexpr u32 BT_NQ = 8;                        // row queues of each mode: one 
 constexpr u32 BT_QSTRIDE = 1088;                // words between two queue counters (4 KiB + 256 bytes)
 constexpr u32 BT_Q1 = 64;                       // per queue: positions taken one at a time first
 constexpr u32 BT_QCHUNK = 4;                    // then this many per grab
-constexpr u32 BT_WAVE_CLS = 11;                 // rows of classes <= this (< 2048 keys): one wave each
-constexpr u32 BT_WAVE_M = 32;                   // their keys per lane at most
+constexpr u32 BT_WAVE_M = 48;                   // wave mode: keys per lane at most
+constexpr u32 BT_WAVE_MAXLEN = BT_WAVE_M * 64;  // rows shorter than this (3072 keys): one wave each
+constexpr u32 BT_WAVE_CLS = 12;                 // the class of BT_WAVE_MAXLEN: rows of classes above
+                                                // it are all longer, of classes below all shorter
 constexpr u32 BT_WQCHUNK = 2;                   // rows per grab of a wave
 constexpr size_t BT_GRAPHS_MAX = 32;            // instantiated graphs kept per context
 
@@ -828,12 +830,14 @@ __device__ __forceinline__ void bt_wave_row(const BtArgs &a, u32 r, const u32 *_
     }
 }
 
-// A row of the wave mode (its class is at most BT_WAVE_CLS).
+// A row of the wave mode's range: solved if shorter than BT_WAVE_MAXLEN (a
+// longer one of the shared class is the workgroup mode's).
 template <bool LARGEST>
 __device__ __forceinline__ void bt_wave_dispatch(const BtArgs &a, u32 r, BtWaveLds &L)
 {
     const u64 off = a.row_off[r];
     const u64 len64 = a.row_off[r + 1] - off;
+    if (len64 >= BT_WAVE_MAXLEN) return;
     const u32 k = a.k[r];
     const u32 cls = len_class(len64);
     if (cls < a.cls_lo || cls > a.cls_hi) return;
@@ -846,6 +850,7 @@ __device__ __forceinline__ void bt_wave_dispatch(const BtArgs &a, u32 r, BtWaveL
     if (len <= 16 * WAVE) bt_wave_row<LARGEST, 16>(a, r, row, len, k, L);
     else if (len <= 32 * WAVE) bt_wave_row<LARGEST, 32>(a, r, row, len, k, L);
     else bt_wave_row<LARGEST, BT_WAVE_M>(a, r, row, len, k, L);
+    static_assert(BT_WAVE_MAXLEN > 32 * WAVE && BT_WAVE_M % 16 == 0, "wave-mode sizes");
 }
 
 template <bool LARGEST>
@@ -854,6 +859,7 @@ __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
     const u32 tid = bt_tid();
     const u64 off = a.row_off[r];
     const u64 len64 = a.row_off[r + 1] - off;
+    if (len64 < BT_WAVE_MAXLEN) return;          // the wave mode's row (shared class)
     const u32 k = a.k[r];
     const u32 cls = len_class(len64);
     if (cls < a.cls_lo || cls > a.cls_hi) return;
@@ -1076,14 +1082,19 @@ __global__ __launch_bounds__(BT_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
     __shared__ BtShared sh;
     for (u32 i = threadIdx.x; i < BT_BINS; i += BT_THREADS) sh.hist[i] = 0u;
     lds_sync();
-    // order positions [0, n_wg): the rows longer than the wave mode's
+    // order positions [0, n_wg): the classes with workgroup rows (longer
+    // than BT_WAVE_MAXLEN); [n_wv0, rows): the classes with wave rows.  The
+    // class of BT_WAVE_MAXLEN is in both ranges, and each mode skips the
+    // other's rows in it.
     if (threadIdx.x == 0) {
-        u32 nw = 0;
-        for (u32 c = BT_WAVE_CLS + 1; c < (u32)BT_NCLS; ++c) nw += a.cls_cnt[c];
-        sh.n_wg = nw;
+        u32 above = 0;
+        for (u32 c = BT_WAVE_CLS + 1; c < (u32)BT_NCLS; ++c) above += a.cls_cnt[c];
+        sh.n_wg = above + a.cls_cnt[BT_WAVE_CLS];
+        sh.next = above;
     }
     lds_sync();
     const u32 n_wg = __builtin_amdgcn_readfirstlane(sh.n_wg);
+    const u32 n_wv0 = __builtin_amdgcn_readfirstlane(sh.next);
     // Workgroup mode: those rows, longest first, from BT_NQ queues, one per
     // XCD (workgroup b is dispatched to XCD b % BT_NQ): queue x hands out the
     // positions x, x + BT_NQ, ... of [0, n_wg), one per grab for the first
@@ -1107,7 +1118,7 @@ __global__ __launch_bounds__(BT_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
             for (u32 q = q0; q < q1; ++q) bt_row<LARGEST>(a, a.order[q * BT_NQ + x], sh);
         }
     }
-    // Wave mode: positions [n_wg, rows), one row per wave, BT_WQCHUNK rows
+    // Wave mode: positions [n_wv0, rows), one row per wave, BT_WQCHUNK rows
     // per grab from the second set of queues (the same queue choice).  No
     // workgroup barrier follows: the waves leave independently.
     const u32 lane = bt_tid() & (WAVE - 1);
@@ -1117,7 +1128,7 @@ __global__ __launch_bounds__(BT_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
         uint4 *hp = reinterpret_cast<uint4 *>(L.hist);
         for (u32 i = lane; i < BT_BINS / 4; i += WAVE) hp[i] = make_uint4(0u, 0u, 0u, 0u);
     }
-    const u32 n_wv = a.rows - n_wg;
+    const u32 n_wv = a.rows - n_wv0;
     for (u32 x = q_first; x < BT_NQ; x += q_step) {
         const u32 nx = n_wv > x ? (n_wv - x + BT_NQ - 1) / BT_NQ : 0u;
         u32 *qc = a.queue + (BT_NQ + x) * BT_QSTRIDE;
@@ -1127,7 +1138,7 @@ __global__ __launch_bounds__(BT_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
             g = __builtin_amdgcn_readfirstlane(g);
             if (g >= nx) break;
             const u32 g1 = g + BT_WQCHUNK < nx ? g + BT_WQCHUNK : nx;
-            for (u32 q = g; q < g1; ++q) bt_wave_dispatch<LARGEST>(a, a.order[n_wg + q * BT_NQ + x], L);
+            for (u32 q = g; q < g1; ++q) bt_wave_dispatch<LARGEST>(a, a.order[n_wv0 + q * BT_NQ + x], L);
         }
     }
 }

@@ -50,7 +50,11 @@ def ragged(lens, ks, gen):
     return keys, off, np.array(ks, np.uint32)
 
 
-MIXED_LENS = [1, 2, 63, 64, 1000, 4095, 4096, 4097, 5000, 8192, 20000, 65537, 150000, 300001]
+# lengths around every boundary: the wave mode's register blocks (1024,
+# 2048 keys) and its limit (3072: longer rows of that class go to a
+# workgroup), the workgroup's register rows (4096, 8192), the sampled rows
+MIXED_LENS = [1, 2, 63, 64, 1000, 1024, 1025, 2047, 2048, 2049, 3071, 3072, 3073, 4095, 4096,
+              4097, 5000, 8192, 20000, 65537, 150000, 300001]
 
 
 def mixed_ks(lens, rng):
