@@ -48,6 +48,10 @@ def cpu_info():
     return model, os.cpu_count()
 
 
+# sources of the first-round sweep kernel (its constants, state layout and code)
+TRAFFIC_SOURCES = ("select.hpp", "select_impl.hpp")
+
+
 def traffic_record(kernel):
     """Measured HBM bytes per launch from a committed rocprofv3 counter summary,
     if it was taken on the current kernel source; else None."""
@@ -56,9 +60,11 @@ def traffic_record(kernel):
         return None
     with open(path) as f:
         rec = json.load(f)
-    src = os.path.join(ROOT, "paper_1502_03942_amd", "csrc", "select_impl.hpp")
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1502_03942_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    sha = h.hexdigest()
     if rec.get("source_sha256") != sha:
         return None
     return rec

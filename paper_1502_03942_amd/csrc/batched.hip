@@ -4,15 +4,16 @@
 // Rows are ordered longest first (a counting sort by floor(log2 len)) and
 // handed out from eight queues (one per XCD, each serving every eighth
 // position of the order) to a persistent grid of 256-thread workgroups: one
-// row per grab for the long rows, 16 per grab afterwards.  One workgroup
+// row per grab for the long rows, BT_QCHUNK per grab afterwards; rows under
+// BT_WAVE_MAXLEN keys go one per wave, from a second set of queues.  One workgroup
 // solves a row by the sampling method of §2 with the workgroup as the
 // machine:
 //   - a row of at most BT_REG_KEYS keys is the base case: its key order words
 //     stay in registers, an exact radix select finds the pair of rank k and
 //     the columns up to it are written in column order;
-//   - a longer row draws a Bernoulli sample of about bt_s_target keys
-//     (geometric skips, one segment per thread) and takes the pivots L, R at
-//     sample ranks k s / len -/+ Delta.  Then one sweep of the row:
+//   - a longer row draws a stratified sample of bt_s_target keys (one
+//     uniform position in each of s equal strata) and takes the pivots L, R
+//     at sample ranks k s / len -/+ Delta.  Then one sweep of the row:
 //       fast form (the keys up to R are expected to fill at most 0.7 of the
 //       LDS): every wave appends the keys <= R of its columns, with the
 //       column, to a region of its own, counting those < L; no barrier until
@@ -57,7 +58,9 @@ constexpr u32 BT_REG_KEYS = 8192;              // a short row: held in registers
 constexpr int BT_BITS = 10;                     // radix digit
 constexpr u32 BT_BINS = 1u << BT_BITS;
 constexpr int BT_BPT = (int)BT_BINS / BT_THREADS;   // histogram bins per thread in the scan
-constexpr int BT_SEG = 16;                      // sample slots per thread (expected bt_s_target / 256 <= 8)
+constexpr int BT_SEG = 8;                       // sample strata per thread (bt_s_target <= 2048)
+static_assert(BT_SEG * BT_THREADS >= 2048 && BT_SEG * BT_THREADS <= BT_CAP,
+              "the largest sample fits the strata slots and the LDS buffer");
 constexpr int BT_IPT = 16;                      // keys per thread per step of the general sweep
 constexpr u32 BT_STEP = BT_THREADS * BT_IPT;
 constexpr int BT_NCLS = 34;                     // length classes 0 (empty) .. 33
@@ -312,39 +315,33 @@ __device__ void bt_emit(SRC src, u32 n, u64 tau, u32 *out, u32 limit, BtShared &
     }
 }
 
-// Geometric-skip Bernoulli sample of a row (rate s_target / len): thread t
-// samples its segment [t L, min(t L + L, len)), L = ceil(len / 256), with
-// skips 1 + floor(ln U / ln(1 - rho)), U from Philox4x32-10 at counter
-// (j / 4, t, tag, row), key = seed; at most BT_SEG per segment.  The skips of
-// a segment are independent, so they are evaluated together (fp32: the
-// sample only guides the pivots) and summed.
-__device__ __forceinline__ int bt_sample(u32 t, u64 len, u32 s_target, u64 seed, u32 tag,
-                                         u32 row, u32 (&pos)[BT_SEG])
+// Stratified sample of a row for the pivots: the row is cut into s equal
+// strata (boundaries floor(q len / s), q = 0 .. s) and one position is drawn
+// uniformly from each, with 32-bit draws of Philox4x32-10 at counter (j / 4,
+// t, tag, row), key = seed.  Thread t takes the strata q = j BT_THREADS + t
+// below s and returns how many.  Against a Bernoulli sample at rate s / len
+// the size is exact and, for any threshold, the number of sampled keys below
+// it has the same mean and no larger variance (a sum of independent draws,
+// one per stratum), so the pivot ranks of §2 keep their guarantee.
+__device__ __forceinline__ int bt_sample(u32 t, u32 len, u32 s, u64 seed, u32 tag, u32 row,
+                                         u32 (&pos)[BT_SEG])
 {
-    const float rho = (float)s_target / (float)len;
-    const u64 L = (len + BT_THREADS - 1) / BT_THREADS;
-    const u64 s0 = (u64)t * L;
-    const u64 e0 = s0 + L < len ? s0 + L : len;
-    if (s0 >= e0) return 0;
-    const float inv = 1.0f / log1pf(-rho);
-    u64 p = s0 - 1;
+    const u64 step = ((u64)len << 32) / s;      // stratum width, 32.32 fixed point
+    const u32 nj = (s + BT_THREADS - 1) / BT_THREADS;
     int cnt = 0;
-    bool past = false;               // this segment is done
 #pragma unroll
     for (int j0 = 0; j0 < BT_SEG; j0 += 4) {
-        if (ballot(!past) == 0) break;   // every segment of the wave is done
+        if ((u32)j0 >= nj) break;
         const uint4 r4 = philox4x32_10(make_uint4((u32)(j0 >> 2), t, tag, row), (u32)seed, (u32)(seed >> 32));
         const u32 w[4] = {r4.x, r4.y, r4.z, r4.w};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int j = j0 + i;
-            const float u = ((float)(w[i] >> 8) + 0.5f) * (1.0f / 16777216.0f);
-            const float q = __logf(u) * inv;
-            const u64 skip = q >= (float)L ? L + 1 : 1 + (u64)q;
-            if (!past) {
-                p += skip;
-                if (p < e0) { pos[j] = (u32)p; cnt = j + 1; }
-                else past = true;
+            const u32 q = (u32)(j0 + i) * BT_THREADS + t;
+            if (q < s) {
+                const u32 b = (u32)(((u64)q * step) >> 32);
+                const u32 e = (u32)(((u64)(q + 1) * step) >> 32);
+                pos[j0 + i] = b + (u32)(((u64)w[i] * (e - b)) >> 32);
+                cnt = j0 + i + 1;
             }
         }
     }
@@ -449,6 +446,43 @@ __device__ __forceinline__ void bt_fast_sweep(const u32 *__restrict__ row, u32 l
     }
     cnt_out = cnt;
     na_out = hl ? na : 0u;          // no lower pivot: nothing lies below it
+}
+
+// Write the columns of the fast sweep's candidates up to tau to out[0 ..)
+// (at most `limit`): wave v's region holds sh.wt[0][v] pairs; the waves'
+// counts are exchanged once, then every wave writes its pairs in region
+// order after those of the waves before it.
+__device__ __forceinline__ void bt_emit_regions(u64 tau, u32 *out, u32 limit, BtShared &sh)
+{
+    const u32 tid = bt_tid(), lane = tid & (WAVE - 1);
+    const u32 w = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    const u32 cw = __builtin_amdgcn_readfirstlane(sh.wt[0][w]);
+    u32 pos = 0;
+    const u64 *reg = sh.buf + w * BT_REG;
+    const u32 nc = (cw + WAVE - 1) / WAVE;          // at most BT_REG / WAVE = 16
+    static_assert(BT_REG / WAVE <= 32, "one selection bit per region column");
+    u32 bits = 0, c = 0;
+    for (u32 j = 0; j < nc; ++j) {
+        const u32 i = j * WAVE + lane;
+        const bool t = i < cw && reg[i] <= tau;
+        bits |= (u32)t << j;
+        c += (u32)__popcll(ballot(t));
+    }
+    if (lane == 0) sh.scan[w] = c;
+    lds_sync();
+#pragma unroll
+    for (int v = 0; v < BT_WAVES; ++v)
+        if ((u32)v < w) pos += __builtin_amdgcn_readfirstlane(sh.scan[v]);
+    for (u32 j = 0; j < nc; ++j) {
+        const bool t = (bits >> j) & 1u;
+        const u64 m = ballot(t);
+        if (t) {
+            const u32 q = pos + mbcnt(m);
+            if (q < limit) out[q] = (u32)reg[j * WAVE + lane];
+        }
+        pos += (u32)__popcll(m);
+    }
+    lds_sync();                    // sh.scan is reused
 }
 
 // Rank `rank` (0-based) among the fast sweep's candidates, the pairs
@@ -671,10 +705,11 @@ __device__ __forceinline__ void bt_reg_emit(const u32 (&o)[M], u32 n, u64 tau, u
     lds_sync();                    // ecnt is reused
 }
 
-// A row of at most M BT_THREADS keys, held in registers as key order words.
+// A row of at most M BT_THREADS keys, held in registers as key order words;
+// thread 0 gets the key bits of the pair of rank k in kbits.
 template <bool LARGEST, int M>
 __device__ __forceinline__ u64 bt_reg_row(const u32 *__restrict__ row, u32 len, u32 k, u32 *out,
-                                          BtShared &sh)
+                                          u32 &kbits, BtShared &sh)
 {
     const u32 tid = bt_tid();
     const u32 jn = (len + BT_THREADS - 1) / BT_THREADS;
@@ -689,6 +724,7 @@ __device__ __forceinline__ u64 bt_reg_row(const u32 *__restrict__ row, u32 len, 
 #pragma unroll
     for (int j = 0; j < M; ++j) o[j] = key_ord<true, LARGEST>(o[j]);
     const u64 tau = bt_reg_select<M>(o, len, k - 1, sh);
+    if (bt_tid() == 0) kbits = row[(u32)tau];      // in flight during the output
     bt_reg_emit<M>(o, len, tau, out, k, sh);
     return tau;
 }
@@ -809,6 +845,8 @@ __device__ __forceinline__ void bt_wave_row(const BtArgs &a, u32 r, const u32 *_
     for (int j = 0; j < M; ++j) o[j] = key_ord<true, LARGEST>(o[j]);
     const u64 tau = bt_wave_select<M>(o, len, k - 1, L);
     const u32 th = (u32)(tau >> 32), tl = (u32)tau;
+    u32 kbits = 0;
+    if (lane == 0) kbits = row[tl];                 // in flight during the output
     u32 *__restrict__ out = a.out_idx + a.out_off[r];
     u32 pos = 0;
 #pragma unroll
@@ -826,7 +864,7 @@ __device__ __forceinline__ void bt_wave_row(const BtArgs &a, u32 r, const u32 *_
     }
     if (lane == 0) {
         a.kth_idx[r] = tl;
-        a.kth_key[r] = row[tl];
+        a.kth_key[r] = kbits;
     }
 }
 
@@ -878,37 +916,37 @@ __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
     };
 
     u32 na = 0, nb = len;
+    u32 kbits = 0;                      // key bits of the pair of rank k (thread 0)
     bool in_lds = false, fast_done = false;
     u64 fast_tau = 0;
     int band_top = 64;                  // pairs in LDS agree at and above this bit
     bool reg_done = false;
     u64 reg_tau = 0;
+    u32 reg_kbits = 0;
     if (len <= BT_REG_KEYS / 8) {
-        reg_tau = bt_reg_row<LARGEST, BT_REG_KEYS / 8 / BT_THREADS>(row, len, k, out, sh);
+        reg_tau = bt_reg_row<LARGEST, BT_REG_KEYS / 8 / BT_THREADS>(row, len, k, out, reg_kbits, sh);
         reg_done = true;
     } else if (len <= BT_REG_KEYS / 2) {
-        reg_tau = bt_reg_row<LARGEST, BT_REG_KEYS / 2 / BT_THREADS>(row, len, k, out, sh);
+        reg_tau = bt_reg_row<LARGEST, BT_REG_KEYS / 2 / BT_THREADS>(row, len, k, out, reg_kbits, sh);
         reg_done = true;
     } else if (len <= BT_REG_KEYS) {
-        reg_tau = bt_reg_row<LARGEST, BT_REG_KEYS / BT_THREADS>(row, len, k, out, sh);
+        reg_tau = bt_reg_row<LARGEST, BT_REG_KEYS / BT_THREADS>(row, len, k, out, reg_kbits, sh);
         reg_done = true;
     } else {
         u32 c_num = a.c_cls[cls];
         const u32 s_target = a.s_cls[cls];
         bool fast_ok = a.fast != 0u;    // until a fast sweep overflows its region
         for (u32 att = 0; att < a.attempts && !in_lds && !fast_done; ++att) {
-            // sample -> LDS, compacted; the keys are loaded before the scan
-            // of the counts, so their latency overlaps its barriers
+            // sample -> LDS: stratum q at slot q
+            const u32 s = s_target < len ? s_target : len;
             u32 pos[BT_SEG], sk[BT_SEG];
-            const int cnt = bt_sample(tid, len, s_target, a.seed, att, r, pos);
-#pragma unroll
-            for (int j = 0; j < BT_SEG; ++j) sk[j] = row[j < cnt ? pos[j] : 0u];
-            u32 s;
-            const u32 at = block_excl_scan<BT_THREADS, true>((u32)cnt, sh.scan, &s);
-            s = __builtin_amdgcn_readfirstlane(s);
+            const int cnt = bt_sample(tid, len, s, a.seed, att, r, pos);
 #pragma unroll
             for (int j = 0; j < BT_SEG; ++j)
-                if (j < cnt) sh.buf[at + (u32)j] = pack(key_ord<true, LARGEST>(sk[j]), pos[j]);
+                if (j < cnt) sk[j] = row[pos[j]];
+#pragma unroll
+            for (int j = 0; j < BT_SEG; ++j)
+                if (j < cnt) sh.buf[(u32)j * BT_THREADS + tid] = pack(key_ord<true, LARGEST>(sk[j]), pos[j]);
             lds_sync();
             i64 lo, hi;
             pivot_ranks(s, k, len, c_num, lo, hi);
@@ -1052,26 +1090,32 @@ __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
     u64 tau;
     const bool one[2] = {true, false};
     u64 t2[2];
+    // the key of the pair of rank k is loaded before the output is written,
+    // so that its latency overlaps the writes
     if (reg_done) {
         tau = reg_tau;
+        kbits = reg_kbits;
     } else if (fast_done) {
         tau = fast_tau;
-        bt_emit(ssrc, BT_CAP, tau, out, k, sh);
+        if (tid == 0) kbits = row[(u32)tau];
+        bt_emit_regions(tau, out, k, sh);       // sh.wt[0] still holds the counts
     } else if (in_lds) {
         const u64 rk[2] = {(u64)(k - na - 1), 0ull};
         bt_select(lsrc, nb, band_top, rk, one, t2, sh);
         tau = t2[0];
+        if (tid == 0) kbits = row[(u32)tau];
         bt_emit(lsrc, nb, tau, out + na, k - na, sh);
     } else {
         // exact fallback over the row
         const u64 rk[2] = {(u64)(k - 1), 0ull};
         bt_select(gsrc, len, 64, rk, one, t2, sh);
         tau = t2[0];
+        if (tid == 0) kbits = row[(u32)tau];
         bt_emit(gsrc, len, tau, out, k, sh);
     }
     if (tid == 0) {
         a.kth_idx[r] = (u32)tau;
-        a.kth_key[r] = (u32)tau < len ? row[(u32)tau] : 0u;
+        a.kth_key[r] = kbits;
     }
     lds_sync();
 }
