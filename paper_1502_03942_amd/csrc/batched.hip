@@ -359,6 +359,60 @@ __device__ __forceinline__ float ord_value(u32 o)
 template <bool LARGEST>
 __device__ __forceinline__ bool ord_is_nan(u32 o) { return (LARGEST ? ~o : o) == 0xFFFFFFFFu; }
 
+// min / max of a u32 over the wave (wave-uniform result)
+template <bool MAX>
+__device__ __forceinline__ u32 bt_wave_ext_u32(u32 v)
+{
+    auto step = [&](auto ctrl_tag, auto rows_tag) {
+        constexpr int C = decltype(ctrl_tag)::value, R = decltype(rows_tag)::value;
+        const u32 x = (u32)__builtin_amdgcn_update_dpp((int)v, (int)v, C, R, 0xF, false);
+        v = MAX ? (x > v ? x : v) : (x < v ? x : v);
+    };
+    step(std::integral_constant<int, DPP_XOR1>(), std::integral_constant<int, 0xF>());
+    step(std::integral_constant<int, DPP_XOR2>(), std::integral_constant<int, 0xF>());
+    step(std::integral_constant<int, DPP_ROW_HALF_MIRROR>(), std::integral_constant<int, 0xF>());
+    step(std::integral_constant<int, DPP_ROW_MIRROR>(), std::integral_constant<int, 0xF>());
+    step(std::integral_constant<int, DPP_ROW_BCAST15>(), std::integral_constant<int, 0xA>());
+    step(std::integral_constant<int, DPP_ROW_BCAST31>(), std::integral_constant<int, 0xC>());
+    return (u32)__builtin_amdgcn_readlane((int)v, WAVE - 1);
+}
+
+// Histogram bins linear in the key value.  g(o), the key value of order
+// word o (negated for largest), is non-decreasing in o; bin(o) = clamp of
+// floor(g(o) scale + bias), one fused multiply-add, is then non-decreasing
+// in o as well (every rounding step is monotone), and every evaluation of
+// it gives the same bin.  So all pairs of a lower bin precede all pairs of a
+// higher one, and equal keys share a bin.
+template <bool LARGEST>
+__device__ __forceinline__ float ord_lin(u32 o)
+{
+    const float v = ord_value<LARGEST>(o);
+    return LARGEST ? -v : v;
+}
+
+template <bool LARGEST>
+__device__ __forceinline__ u32 lin_bin(u32 o, float scale, float bias)
+{
+    const float t = fmaxf(__builtin_fmaf(ord_lin<LARGEST>(o), scale, bias), 0.0f);
+    const u32 b = (u32)t;
+    return b < BT_BINS - 1 ? b : BT_BINS - 1;
+}
+
+// Bins over the order words [omin, omax]: false if the range holds a NaN,
+// an infinity or a single value (the radix select handles those).
+template <bool LARGEST>
+__device__ __forceinline__ bool lin_setup(u32 omin, u32 omax, float &scale, float &bias)
+{
+    if (omin >= omax || ord_is_nan<LARGEST>(omin) || ord_is_nan<LARGEST>(omax)) return false;
+    const float g0 = ord_lin<LARGEST>(omin), g1 = ord_lin<LARGEST>(omax);
+    const float span = g1 - g0;
+    if (!(span > 0.0f) || !__builtin_isfinite(g0) || !__builtin_isfinite(g1) || !__builtin_isfinite(span))
+        return false;
+    scale = (float)(BT_BINS - 1) / span;
+    bias = -g0 * scale;
+    return __builtin_isfinite(scale) && __builtin_isfinite(bias);
+}
+
 // IPT keys per lane of one sweep step (the tile: BT_THREADS * IPT keys),
 // interleaved so that wave w holds columns s0 + (j * BT_WAVES + w) * 64 + lane.
 template <bool GUARD, int IPT>
@@ -662,9 +716,99 @@ __device__ __forceinline__ u64 bt_reg_select(const u32 (&o)[M], u32 n, u32 rank,
     return sh.found[0];
 }
 
+// First try for a row held in registers: one histogram pass over bins
+// linear in the key value between the row's least and greatest key, then,
+// if the bin holding rank `rank` has at most 64 pairs, one wave ranks them.
+// Returns false, every bin left at zero, when the range allows no linear
+// bins or the bin is larger; the radix select then decides.
+template <bool LARGEST, int M>
+__device__ __forceinline__ bool bt_reg_lin(const u32 (&o)[M], u32 n, u32 rank, BtShared &sh, u64 &tau)
+{
+    const u32 tid = bt_tid(), lane = tid & (WAVE - 1);
+    const u32 w = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    const u32 jn = (n + BT_THREADS - 1) / BT_THREADS;
+    u32 mn = ~0u, mx = 0u;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        if ((u32)j < jn && (u32)j * BT_THREADS + tid < n) {
+            mn = o[j] < mn ? o[j] : mn;
+            mx = o[j] > mx ? o[j] : mx;
+        }
+    }
+    mn = bt_wave_ext_u32<false>(mn);
+    mx = bt_wave_ext_u32<true>(mx);
+    if (lane == 0) {
+        sh.wt[0][w] = mn;
+        sh.wt[1][w] = mx;
+    }
+    if (tid == 0) sh.ccount[0] = 0u;
+    lds_sync();
+    u32 omin = ~0u, omax = 0u;
+#pragma unroll
+    for (int v = 0; v < BT_WAVES; ++v) {
+        const u32 a0 = __builtin_amdgcn_readfirstlane(sh.wt[0][v]);
+        const u32 a1 = __builtin_amdgcn_readfirstlane(sh.wt[1][v]);
+        omin = a0 < omin ? a0 : omin;
+        omax = a1 > omax ? a1 : omax;
+    }
+    float scale, bias;
+    if (!lin_setup<LARGEST>(omin, omax, scale, bias)) return false;
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+        if ((u32)j < jn && (u32)j * BT_THREADS + tid < n)
+            atomicAdd(&sh.hist[lin_bin<LARGEST>(o[j], scale, bias)], 1u);
+    lds_sync();
+    u32 c[BT_BPT], csum = 0;
+#pragma unroll
+    for (int q = 0; q < BT_BPT; ++q) {
+        c[q] = sh.hist[tid * BT_BPT + q];
+        sh.hist[tid * BT_BPT + q] = 0u;
+        csum += c[q];
+    }
+    u32 tot;
+    u32 before = block_excl_scan<BT_THREADS, true>(csum, sh.scan, &tot);
+#pragma unroll
+    for (int q = 0; q < BT_BPT; ++q) {
+        if (before <= rank && rank < before + c[q]) {
+            sh.sel_bin[0] = tid * BT_BPT + q;
+            sh.sel_before[0] = before;
+            sh.sel_count[0] = c[q];
+        }
+        before += c[q];
+    }
+    lds_sync();
+    const u32 b = __builtin_amdgcn_readfirstlane(sh.sel_bin[0]);
+    const u32 cnt = __builtin_amdgcn_readfirstlane(sh.sel_count[0]);
+    const u32 rr = rank - __builtin_amdgcn_readfirstlane(sh.sel_before[0]);
+    if (cnt > (u32)WAVE) return false;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const u32 col = (u32)j * BT_THREADS + tid;
+        if ((u32)j < jn && col < n && lin_bin<LARGEST>(o[j], scale, bias) == b)
+            sh.cand[0][atomicAdd(&sh.ccount[0], 1u)] = pack(o[j], col);
+    }
+    lds_sync();
+    if (w == 0) {
+        const u64 mine = lane < cnt ? sh.cand[0][lane] : ~0ull;
+        const u32 mlo = (u32)mine, mhi = (u32)(mine >> 32);
+        u32 lt = 0;
+        for (u32 i = 0; i < cnt; ++i) {
+            const u64 x = ((u64)(u32)__builtin_amdgcn_readlane((int)mhi, (int)i) << 32) |
+                          (u32)__builtin_amdgcn_readlane((int)mlo, (int)i);
+            lt += x < mine ? 1u : 0u;
+        }
+        if (lane < cnt && lt == rr) sh.found[0] = mine;
+    }
+    lds_sync();
+    tau = sh.found[0];
+    return true;
+}
+
 // Write the columns of the register pairs <= tau in column order to out[0 ..)
-// (at most `limit`): per column block j the waves' counts go to LDS, one
-// barrier, then each wave writes at its place.
+// (at most `limit`): lane j of each wave keeps the wave's count of column
+// block j, the counts go to LDS in one store, and after one barrier lane j
+// finds where the wave's pairs of block j start (the blocks before it, then
+// the waves before this one in block j).
 template <int M>
 __device__ __forceinline__ void bt_reg_emit(const u32 (&o)[M], u32 n, u64 tau, u32 *out, u32 limit,
                                             BtShared &sh)
@@ -673,8 +817,8 @@ __device__ __forceinline__ void bt_reg_emit(const u32 (&o)[M], u32 n, u64 tau, u
     const u32 w = __builtin_amdgcn_readfirstlane(tid / WAVE);
     const u32 jn = (n + BT_THREADS - 1) / BT_THREADS;
     const u32 th = (u32)(tau >> 32), tl = (u32)tau;
-    static_assert(M <= 32, "one selection bit per column block");
-    u32 bits = 0;
+    static_assert(M <= 32 && BT_WAVES == 4, "one selection bit per column block; four waves");
+    u32 bits = 0, myc = 0;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
         if ((u32)j < jn) {
@@ -682,24 +826,29 @@ __device__ __forceinline__ void bt_reg_emit(const u32 (&o)[M], u32 n, u64 tau, u
             const bool t = col < n && (o[j] < th || (o[j] == th && col <= tl));
             bits |= (u32)t << j;
             const u32 c = (u32)__popcll(ballot(t));
-            if (lane == 0) sh.ecnt[j][w] = c;
+            myc = lane == (u32)j ? c : myc;
         }
     }
+    if (lane < jn) sh.ecnt[lane][w] = myc;
     lds_sync();
-    u32 pos = 0;
+    u32 all = 0, mine = 0;
+    if (lane < jn) {
+        const uint4 c4 = *(const uint4 *)sh.ecnt[lane];
+        all = c4.x + c4.y + c4.z + c4.w;
+        mine = (w > 0 ? c4.x : 0u) + (w > 1 ? c4.y : 0u) + (w > 2 ? c4.z : 0u);
+    }
+    const u32 incl = wave_incl_scan(all);
+    const u32 off = incl - all + mine;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
         if ((u32)j < jn) {
             const bool t = (bits >> j) & 1u;
             const u64 m = ballot(t);
-            const uint4 c4 = *(const uint4 *)sh.ecnt[j];
-            const u32 all = c4.x + c4.y + c4.z + c4.w;
-            const u32 mine = pos + (w > 0 ? c4.x : 0u) + (w > 1 ? c4.y : 0u) + (w > 2 ? c4.z : 0u);
+            const u32 base = (u32)__builtin_amdgcn_readlane((int)off, j);
             if (t) {
-                const u32 q = mine + mbcnt(m);
+                const u32 q = base + mbcnt(m);
                 if (q < limit) out[q] = (u32)j * BT_THREADS + tid;
             }
-            pos += all;
         }
     }
     lds_sync();                    // ecnt is reused
@@ -723,7 +872,8 @@ __device__ __forceinline__ u64 bt_reg_row(const u32 *__restrict__ row, u32 len, 
     }
 #pragma unroll
     for (int j = 0; j < M; ++j) o[j] = key_ord<true, LARGEST>(o[j]);
-    const u64 tau = bt_reg_select<M>(o, len, k - 1, sh);
+    u64 tau;
+    if (!bt_reg_lin<LARGEST, M>(o, len, k - 1, sh, tau)) tau = bt_reg_select<M>(o, len, k - 1, sh);
     if (bt_tid() == 0) kbits = row[(u32)tau];      // in flight during the output
     bt_reg_emit<M>(o, len, tau, out, k, sh);
     return tau;
@@ -891,6 +1041,93 @@ __device__ __forceinline__ void bt_wave_dispatch(const BtArgs &a, u32 r, BtWaveL
     static_assert(BT_WAVE_MAXLEN > 32 * WAVE && BT_WAVE_M % 16 == 0, "wave-mode sizes");
 }
 
+// Pivots from the sample by bins linear in the key value.  The sample pairs
+// are each thread's (o[j], p[j]), j < cnt; the waves' least and greatest
+// order words are in sh.wt[0][], sh.wt[1][] and both candidate counters are
+// zero.  One histogram serves both target ranks; when each active target's
+// bin holds at most 64 pairs, waves 0 and 1 rank them.  Returns false, every
+// bin left at zero, if the range allows no linear bins or a bin is larger.
+template <bool LARGEST>
+__device__ __forceinline__ bool bt_pivots_lin(const u32 (&o)[BT_SEG], const u32 (&p)[BT_SEG], int cnt,
+                                              const u64 rank[2], const bool act[2], u64 res[2], BtShared &sh)
+{
+    const u32 tid = bt_tid(), lane = tid & (WAVE - 1);
+    const u32 w = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    u32 omin = ~0u, omax = 0u;
+#pragma unroll
+    for (int v = 0; v < BT_WAVES; ++v) {
+        const u32 a0 = __builtin_amdgcn_readfirstlane(sh.wt[0][v]);
+        const u32 a1 = __builtin_amdgcn_readfirstlane(sh.wt[1][v]);
+        omin = a0 < omin ? a0 : omin;
+        omax = a1 > omax ? a1 : omax;
+    }
+    float scale, bias;
+    if (!lin_setup<LARGEST>(omin, omax, scale, bias)) return false;
+#pragma unroll
+    for (int j = 0; j < BT_SEG; ++j)
+        if (j < cnt) atomicAdd(&sh.hist[lin_bin<LARGEST>(o[j], scale, bias)], 1u);
+    lds_sync();
+    u32 c[BT_BPT], csum = 0;
+#pragma unroll
+    for (int q = 0; q < BT_BPT; ++q) {
+        c[q] = sh.hist[tid * BT_BPT + q];
+        sh.hist[tid * BT_BPT + q] = 0u;
+        csum += c[q];
+    }
+    u32 tot;
+    u32 before = block_excl_scan<BT_THREADS, true>(csum, sh.scan, &tot);
+#pragma unroll
+    for (int q = 0; q < BT_BPT; ++q) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            if (act[t] && (u64)before <= rank[t] && rank[t] < (u64)before + c[q]) {
+                sh.sel_bin[t] = tid * BT_BPT + q;
+                sh.sel_before[t] = before;
+                sh.sel_count[t] = c[q];
+            }
+        }
+        before += c[q];
+    }
+    lds_sync();
+    u32 b[2] = {0u, 0u}, nb[2] = {0u, 0u}, rr[2] = {0u, 0u};
+    bool big = false;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        if (!act[t]) continue;
+        b[t] = __builtin_amdgcn_readfirstlane(sh.sel_bin[t]);
+        nb[t] = __builtin_amdgcn_readfirstlane(sh.sel_count[t]);
+        rr[t] = (u32)rank[t] - __builtin_amdgcn_readfirstlane(sh.sel_before[t]);
+        big = big || nb[t] > (u32)WAVE;
+    }
+    if (big) return false;
+#pragma unroll
+    for (int j = 0; j < BT_SEG; ++j) {
+        if (j < cnt) {
+            const u32 bn = lin_bin<LARGEST>(o[j], scale, bias);
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                if (act[t] && bn == b[t]) sh.cand[t][atomicAdd(&sh.ccount[t], 1u)] = pack(o[j], p[j]);
+        }
+    }
+    lds_sync();
+    if (w < 2 && act[w]) {
+        const u32 m = nb[w] , want = rr[w];
+        const u64 mine = lane < m ? sh.cand[w][lane] : ~0ull;
+        const u32 mlo = (u32)mine, mhi = (u32)(mine >> 32);
+        u32 lt = 0;
+        for (u32 i = 0; i < m; ++i) {
+            const u64 x = ((u64)(u32)__builtin_amdgcn_readlane((int)mhi, (int)i) << 32) |
+                          (u32)__builtin_amdgcn_readlane((int)mlo, (int)i);
+            lt += x < mine ? 1u : 0u;
+        }
+        if (lane < m && lt == want) sh.found[w] = mine;
+    }
+    lds_sync();
+    res[0] = act[0] ? sh.found[0] : 0ull;
+    res[1] = act[1] ? sh.found[1] : 0ull;
+    return true;
+}
+
 template <bool LARGEST>
 __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
 {
@@ -937,16 +1174,34 @@ __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
         const u32 s_target = a.s_cls[cls];
         bool fast_ok = a.fast != 0u;    // until a fast sweep overflows its region
         for (u32 att = 0; att < a.attempts && !in_lds && !fast_done; ++att) {
-            // sample -> LDS: stratum q at slot q
+            // sample -> LDS (stratum q at slot q) and registers, with the
+            // waves' least and greatest order words
             const u32 s = s_target < len ? s_target : len;
             u32 pos[BT_SEG], sk[BT_SEG];
             const int cnt = bt_sample(tid, len, s, a.seed, att, r, pos);
 #pragma unroll
             for (int j = 0; j < BT_SEG; ++j)
                 if (j < cnt) sk[j] = row[pos[j]];
+            u32 mn = ~0u, mx = 0u;
 #pragma unroll
-            for (int j = 0; j < BT_SEG; ++j)
-                if (j < cnt) sh.buf[(u32)j * BT_THREADS + tid] = pack(key_ord<true, LARGEST>(sk[j]), pos[j]);
+            for (int j = 0; j < BT_SEG; ++j) {
+                if (j < cnt) {
+                    sk[j] = key_ord<true, LARGEST>(sk[j]);
+                    sh.buf[(u32)j * BT_THREADS + tid] = pack(sk[j], pos[j]);
+                    mn = sk[j] < mn ? sk[j] : mn;
+                    mx = sk[j] > mx ? sk[j] : mx;
+                }
+            }
+            mn = bt_wave_ext_u32<false>(mn);
+            mx = bt_wave_ext_u32<true>(mx);
+            {
+                const u32 ln = tid & (WAVE - 1), wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
+                if (ln == 0) {
+                    sh.wt[0][wv] = mn;
+                    sh.wt[1][wv] = mx;
+                }
+            }
+            if (tid < 2) sh.ccount[tid] = 0u;
             lds_sync();
             i64 lo, hi;
             pivot_ranks(s, k, len, c_num, lo, hi);
@@ -955,7 +1210,8 @@ __device__ __forceinline__ void bt_row(const BtArgs &a, u32 r, BtShared &sh)
             {
                 const u64 rk[2] = {hl ? (u64)lo : 0ull, hr ? (u64)hi : 0ull};
                 const bool ac[2] = {hl, hr};
-                bt_select(lsrc, s, 64, rk, ac, piv, sh);
+                if (!bt_pivots_lin<LARGEST>(sk, pos, cnt, rk, ac, piv, sh))
+                    bt_select(lsrc, s, 64, rk, ac, piv, sh);
             }
             const u64 L = hl ? uniform64(piv[0]) : 0ull;
             const u64 R = hr ? uniform64(piv[1]) : ~0ull;

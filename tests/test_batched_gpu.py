@@ -81,6 +81,49 @@ def test_batched_mixed(dev, largest, dist):
     check_rows(keys, off, kk, res, largest)
 
 
+def edge_rows(n, seed):
+    """Rows without NaN whose key ranges stress bins linear in the key value:
+    extremes whose difference overflows, infinite or denormal extremes, two
+    values, ties inside a bin, sorted and narrow ranges, mixed zeros."""
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal(n).astype(np.float32)
+    rows = []
+    r = g.copy(); r[rng.integers(0, n)] = 3.4028235e38; r[rng.integers(0, n)] = -3.4028235e38
+    rows.append(r)                                            # span overflows to inf
+    r = np.abs(g); r[rng.integers(0, n)] = 3.4028235e38
+    rows.append(r)                                            # finite span, one huge bin
+    r = g.copy(); r[rng.integers(0, n)] = np.inf; r[rng.integers(0, n)] = -np.inf
+    rows.append(r)                                            # infinite extremes
+    rows.append((rng.integers(1, 900, n).astype(np.uint32)).view(np.float32))   # denormals only
+    rows.append(np.where(rng.random(n) < 0.3, 0.0, 1.0).astype(np.float32))   # two values
+    rows.append(np.round(g * 1000.0).astype(np.float32) / np.float32(1000.0))  # ties in bins
+    rows.append(np.sort(g))                                   # sorted
+    rows.append((1.0 + np.arange(n, dtype=np.float32)[::-1] * np.float32(1e-7)).astype(np.float32))
+    r = g.copy(); r[rng.random(n) < 0.2] = 0.0; r[rng.random(n) < 0.2] = -0.0
+    rows.append(r)                                            # +0 and -0 among the keys
+    rows.append(np.exp(rng.standard_normal(n) * 8.0).astype(np.float32))       # heavy tail
+    return rows
+
+
+@pytest.mark.parametrize("largest", [False, True])
+@pytest.mark.parametrize("n", [700, 3000, 3073, 5000, 8192])
+def test_batched_value_range_edges(dev, n, largest):
+    # rows of the wave mode (under 3072 keys) and of the workgroup's register
+    # rows (up to 8192): every row without NaN, so each reaches the value
+    # binning and, where its range allows none or a bin is too full, the
+    # radix select behind it
+    rows = edge_rows(n, 40 + n)
+    rng = np.random.default_rng(41)
+    ks = [int(x) for x in rng.integers(1, n + 1, len(rows))]
+    ks[0], ks[1] = 1, n
+    off = np.zeros(len(rows) + 1, np.uint64)
+    off[1:] = np.cumsum([len(r) for r in rows])
+    keys = np.concatenate(rows).astype(np.float32)
+    kk = np.array(ks, np.uint32)
+    res = tk.Context(0, seed=5).select_batched(*to_dev(keys, off, kk, dev), largest=largest)
+    check_rows(keys, off, kk, res, largest)
+
+
 def test_batched_every_k_small_rows(dev):
     lens = [37] * 37
     ks = list(range(1, 38))
