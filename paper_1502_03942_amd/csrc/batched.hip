@@ -390,17 +390,17 @@ __device__ __forceinline__ float ord_lin(u32 o)
     return LARGEST ? -v : v;
 }
 
-template <bool LARGEST>
+template <bool LARGEST, u32 NB = BT_BINS>
 __device__ __forceinline__ u32 lin_bin(u32 o, float scale, float bias)
 {
     const float t = fmaxf(__builtin_fmaf(ord_lin<LARGEST>(o), scale, bias), 0.0f);
     const u32 b = (u32)t;
-    return b < BT_BINS - 1 ? b : BT_BINS - 1;
+    return b < NB - 1 ? b : NB - 1;
 }
 
-// Bins over the order words [omin, omax]: false if the range holds a NaN,
-// an infinity or a single value (the radix select handles those).
-template <bool LARGEST>
+// NB bins over the order words [omin, omax]: false if the range holds a
+// NaN, an infinity or a single value (the radix select handles those).
+template <bool LARGEST, u32 NB = BT_BINS>
 __device__ __forceinline__ bool lin_setup(u32 omin, u32 omax, float &scale, float &bias)
 {
     if (omin >= omax || ord_is_nan<LARGEST>(omin) || ord_is_nan<LARGEST>(omax)) return false;
@@ -408,7 +408,7 @@ __device__ __forceinline__ bool lin_setup(u32 omin, u32 omax, float &scale, floa
     const float span = g1 - g0;
     if (!(span > 0.0f) || !__builtin_isfinite(g0) || !__builtin_isfinite(g1) || !__builtin_isfinite(span))
         return false;
-    scale = (float)(BT_BINS - 1) / span;
+    scale = (float)(NB - 1) / span;
     bias = -g0 * scale;
     return __builtin_isfinite(scale) && __builtin_isfinite(bias);
 }
@@ -536,7 +536,7 @@ __device__ __forceinline__ void bt_emit_regions(u64 tau, u32 *out, u32 limit, Bt
         }
         pos += (u32)__popcll(m);
     }
-    lds_sync();                    // sh.scan is reused
+    // sh.scan is next written after the barrier that ends the row
 }
 
 // Rank `rank` (0-based) among the fast sweep's candidates, the pairs
@@ -851,7 +851,7 @@ __device__ __forceinline__ void bt_reg_emit(const u32 (&o)[M], u32 n, u64 tau, u
             }
         }
     }
-    lds_sync();                    // ecnt is reused
+    // ecnt is next written after the barrier that ends the row
 }
 
 // A row of at most M BT_THREADS keys, held in registers as key order words;
@@ -977,6 +977,83 @@ __device__ __forceinline__ u64 bt_wave_select(const u32 (&o)[M], u32 n, u32 rank
            (u32)__builtin_amdgcn_readlane((int)mlo, fl);
 }
 
+// First try of the wave mode (a row of more than 64 keys): one histogram of
+// BT_WAVE_LIN bins linear in the key value between the row's least and
+// greatest key; if the bin holding rank `rank` has at most 64 pairs they are
+// compacted and ranked.  Returns false, every bin left at zero, when the
+// range allows no linear bins or the bin is larger.
+constexpr u32 BT_WAVE_LIN = 256;
+template <bool LARGEST, int M>
+__device__ __forceinline__ bool bt_wave_lin(const u32 (&o)[M], u32 n, u32 rank, BtWaveLds &L, u64 &tau)
+{
+    const u32 lane = bt_tid() & (WAVE - 1);
+    const u32 jn = (n + WAVE - 1) / WAVE;
+    u32 mn = ~0u, mx = 0u;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        if ((u32)j < jn && (u32)j * WAVE + lane < n) {
+            mn = o[j] < mn ? o[j] : mn;
+            mx = o[j] > mx ? o[j] : mx;
+        }
+    }
+    mn = bt_wave_ext_u32<false>(mn);
+    mx = bt_wave_ext_u32<true>(mx);
+    float scale, bias;
+    if (!lin_setup<LARGEST, BT_WAVE_LIN>(mn, mx, scale, bias)) return false;
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+        if ((u32)j < jn && (u32)j * WAVE + lane < n)
+            atomicAdd(&L.hist[lin_bin<LARGEST, BT_WAVE_LIN>(o[j], scale, bias)], 1u);
+    // lane l scans bins [4 l, 4 l + 4) and leaves them at zero
+    static_assert(BT_WAVE_LIN == 4 * WAVE, "four bins per lane");
+    uint4 *hp = reinterpret_cast<uint4 *>(&L.hist[lane * 4]);
+    const uint4 v = *hp;
+    *hp = make_uint4(0u, 0u, 0u, 0u);
+    const u32 c[4] = {v.x, v.y, v.z, v.w};
+    const u32 csum = v.x + v.y + v.z + v.w;
+    const u32 incl = wave_incl_scan(csum);
+    u32 before = incl - csum;
+    const bool hit = before <= rank && rank < incl;
+    u32 bin = 0, bcnt = 0, bbefore = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (before <= rank && rank < before + c[q]) {
+            bin = lane * 4 + (u32)q;
+            bcnt = c[q];
+            bbefore = before;
+        }
+        before += c[q];
+    }
+    const int hl = __builtin_ctzll(ballot(hit));
+    const u32 b = (u32)__builtin_amdgcn_readlane((int)bin, hl);
+    const u32 cnt = (u32)__builtin_amdgcn_readlane((int)bcnt, hl);
+    const u32 rk = rank - (u32)__builtin_amdgcn_readlane((int)bbefore, hl);
+    if (cnt > (u32)WAVE) return false;
+    u32 base = 0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        if ((u32)j < jn) {
+            const u32 col = (u32)j * WAVE + lane;
+            const bool t = col < n && lin_bin<LARGEST, BT_WAVE_LIN>(o[j], scale, bias) == b;
+            const u64 m = ballot(t);
+            if (t) L.cand[base + mbcnt(m)] = pack(o[j], col);
+            base += (u32)__popcll(m);
+        }
+    }
+    const u64 mine = lane < cnt ? L.cand[lane] : ~0ull;
+    const u32 mlo = (u32)mine, mhi = (u32)(mine >> 32);
+    u32 lt = 0;
+    for (u32 i = 0; i < cnt; ++i) {
+        const u64 x = ((u64)(u32)__builtin_amdgcn_readlane((int)mhi, (int)i) << 32) |
+                      (u32)__builtin_amdgcn_readlane((int)mlo, (int)i);
+        lt += x < mine ? 1u : 0u;
+    }
+    const int fl = __builtin_ctzll(ballot(lane < cnt && lt == rk));
+    tau = ((u64)(u32)__builtin_amdgcn_readlane((int)mhi, fl) << 32) |
+          (u32)__builtin_amdgcn_readlane((int)mlo, fl);
+    return true;
+}
+
 // One row by one wave: load, select, write the columns up to the pair of
 // rank k in column order (ballot compaction, no LDS), and the k-th pair.
 template <bool LARGEST, int M>
@@ -993,7 +1070,9 @@ __device__ __forceinline__ void bt_wave_row(const BtArgs &a, u32 r, const u32 *_
     }
 #pragma unroll
     for (int j = 0; j < M; ++j) o[j] = key_ord<true, LARGEST>(o[j]);
-    const u64 tau = bt_wave_select<M>(o, len, k - 1, L);
+    u64 tau;
+    if (len <= (u32)WAVE || !bt_wave_lin<LARGEST, M>(o, len, k - 1, L, tau))
+        tau = bt_wave_select<M>(o, len, k - 1, L);
     const u32 th = (u32)(tau >> 32), tl = (u32)tau;
     u32 kbits = 0;
     if (lane == 0) kbits = row[tl];                 // in flight during the output
