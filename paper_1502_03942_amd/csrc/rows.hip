@@ -1,7 +1,9 @@
 // Row-wise top-k of a score matrix (forward) and the scatter of its gradient
 // (backward): the form of the selection a differentiable layer needs.
 //
-// Forward, one 1024-thread workgroup per row, the row in registers.  In the
+// Forward, one 1024-thread workgroup per row, the row in registers (at most
+// 64 registers a thread, so that two rows share a CU and one row's loads
+// overlap the other's selection).  In the
 // selection order of the whole library (composite key (ord, position), §2:
 // ties broken by the object), the row's k first elements are found as
 // follows.  Every thread takes the first of its own keys; every wave
@@ -25,7 +27,6 @@
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
-#include "radix.hpp"
 #include "../../include/topk.h"
 
 namespace topk {
@@ -38,15 +39,39 @@ constexpr int RB_THREADS = 256;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+constexpr int RW_BITS = 10;              // radix digit of the repeated-keys path
+constexpr u32 RW_BINS = 1u << RW_BITS;   // one bin per thread
+static_assert(RW_BINS == RW_THREADS, "one histogram bin per thread");
+
 struct RowShared {
-    RadixShared rs;
+    u32 hist[RW_BINS];                   // zero outside the radix select
     u64 cand[RW_CAND];
     u64 wthr[RW_THREADS / WAVE];
-    u32 ccount;
+    u64 rcand[WAVE];
+    u32 scan[RW_THREADS / WAVE];
+    u32 ccount, rcount, sel_bin, sel_before, sel_count;
+    u64 found;
 };
 
+// The thread index through an empty asm: each loop recomputes its columns
+// (one add) instead of the compiler keeping every column of the row live
+// across the kernel.
+__device__ __forceinline__ u32 opaque(u32 x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// pack(ord, col) into LDS as two 32-bit stores (no 64-bit register pair)
+__device__ __forceinline__ void store_pair(u64 *dst, u32 ord, u32 col)
+{
+    u32 *d = reinterpret_cast<u32 *>(dst);
+    d[0] = col;
+    d[1] = ord;
+}
+
 // Append the lanes with `take` to the LDS candidate list (one atomic per wave).
-__device__ __forceinline__ void cand_append(RowShared &sh, bool take, u64 c)
+__device__ __forceinline__ void cand_append(RowShared &sh, bool take, u32 ord, u32 col)
 {
     const u64 m = ballot(take);
     if (!m) return;
@@ -56,8 +81,84 @@ __device__ __forceinline__ void cand_append(RowShared &sh, bool take, u64 c)
     base = __shfl(base, first, WAVE);
     if (take) {
         const u32 q = base + mbcnt(m);
-        if (q < RW_CAND) sh.cand[q] = c;
+        if (q < RW_CAND) store_pair(&sh.cand[q], ord, col);
     }
+}
+
+// Pair of rank `rank` (0-based) among the row's pairs (o[e], e RW_THREADS +
+// tid), valid below column N: radix select over windows of RW_BITS bits of
+// the 64-bit pair from the top, keeping the bucket that holds the rank, until
+// it has at most 64 pairs, which one wave ranks.  The order words stay in
+// the registers they were loaded into (no 64-bit copies).
+template <int IPT>
+__device__ __forceinline__ u64 rw_select(const u32 (&o)[IPT], u32 N, u32 rank, RowShared &sh)
+{
+    const u32 tid = threadIdx.x, lane = lane_id();
+    const u32 w = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    u32 ph = 0, pl = 0;                 // bits at and above lowb are fixed
+    int lowb = 64;
+    u32 rk = rank, cnt = N;
+    auto match = [&](u32 oj, u32 col) -> bool {
+        if (lowb >= 64) return true;
+        if (lowb >= 32) return (oj >> (lowb - 32)) == (ph >> (lowb - 32));
+        return oj == ph && (col >> lowb) == (pl >> lowb);
+    };
+    while (cnt > (u32)WAVE && lowb > 0) {
+        const int sh_ = lowb > RW_BITS ? lowb - RW_BITS : 0;
+        const u32 tb = opaque(tid);
+#pragma unroll
+        for (int e = 0; e < IPT; ++e) {
+            const u32 col = (u32)e * RW_THREADS + tb;
+            if (col < N && match(o[e], col)) {
+                // bits [sh_, sh_ + RW_BITS) of the pair (o, col), from the two
+                // 32-bit halves (no 64-bit register pair)
+                const u32 d = (sh_ >= 32 ? o[e] >> (sh_ - 32)
+                                         : __builtin_amdgcn_alignbit(o[e], col, (u32)sh_)) & (RW_BINS - 1);
+                atomicAdd(&sh.hist[d], 1u);
+            }
+        }
+        __syncthreads();
+        const u32 c = sh.hist[tid];
+        sh.hist[tid] = 0u;
+        u32 tot;
+        const u32 before = block_excl_scan<RW_THREADS>(c, sh.scan, &tot);
+        if (before <= rk && rk < before + c) {
+            sh.sel_bin = tid;
+            sh.sel_before = before;
+            sh.sel_count = c;
+        }
+        __syncthreads();
+        const u64 bsel = (u64)__builtin_amdgcn_readfirstlane(sh.sel_bin) << sh_;
+        cnt = __builtin_amdgcn_readfirstlane(sh.sel_count);
+        rk -= __builtin_amdgcn_readfirstlane(sh.sel_before);
+        ph |= (u32)(bsel >> 32);
+        pl |= (u32)bsel;
+        lowb = sh_;
+        __syncthreads();                // sel_* are rewritten by the next pass
+    }
+    if (lowb == 0) return ((u64)ph << 32) | pl;
+    if (tid == 0) sh.rcount = 0u;
+    __syncthreads();
+    const u32 tb = opaque(tid);
+#pragma unroll
+    for (int e = 0; e < IPT; ++e) {
+        const u32 col = (u32)e * RW_THREADS + tb;
+        if (col < N && match(o[e], col)) store_pair(&sh.rcand[atomicAdd(&sh.rcount, 1u)], o[e], col);
+    }
+    __syncthreads();
+    if (w == 0) {
+        const u64 mine = lane < cnt ? sh.rcand[lane] : ~0ull;
+        const u32 mlo = (u32)mine, mhi = (u32)(mine >> 32);
+        u32 lt = 0;
+        for (u32 i = 0; i < cnt; ++i) {
+            const u64 x = ((u64)(u32)__builtin_amdgcn_readlane((int)mhi, (int)i) << 32) |
+                          (u32)__builtin_amdgcn_readlane((int)mlo, (int)i);
+            lt += x < mine ? 1u : 0u;
+        }
+        if (lane < cnt && lt == rk) sh.found = mine;
+    }
+    __syncthreads();
+    return sh.found;
 }
 
 template <int IPT, bool LARGEST>
@@ -73,28 +174,31 @@ __global__ __launch_bounds__(RW_THREADS) void k_rows_fwd(const u32 *__restrict__
 
     // element e of thread t is column e * 1024 + t (coalesced loads); every
     // load is issued before the first is used (a column past the row reads
-    // the row's last key, then is marked empty)
+    // the row's last key)
     u32 o[IPT];
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
         const u32 col = (u32)e * RW_THREADS + tid;
         o[e] = __builtin_nontemporal_load(p + (col < N ? col : N - 1));
     }
+    // (a column past the row holds the image of the row's last key; every
+    // later step checks the column against N)
+#pragma unroll
+    for (int e = 0; e < IPT; ++e) o[e] = key_ord<true, LARGEST>(o[e]);
+    // the thread's first pair: columns ascend with e, so the first of equal
+    // order words is the one with the lowest column (32-bit compares; the
+    // 64-bit pairs are formed only where a candidate is stored)
+    u32 mo = 0xFFFFFFFFu, mcol = 0xFFFFFFFFu;
+    const u32 tb0 = opaque(tid);
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
-        const u32 col = (u32)e * RW_THREADS + tid;
-        o[e] = col < N ? key_ord<true, LARGEST>(o[e]) : 0xFFFFFFFFu;
+        const u32 col = (u32)e * RW_THREADS + tb0;
+        if (col < N && (mcol == 0xFFFFFFFFu || o[e] < mo)) {
+            mo = o[e];
+            mcol = col;
+        }
     }
-    auto comp = [&](int e) -> u64 {
-        const u32 col = (u32)e * RW_THREADS + tid;
-        return col < N ? pack(o[e], col) : ~0ull;
-    };
-    u64 m = ~0ull;
-#pragma unroll
-    for (int e = 0; e < IPT; ++e) {
-        const u64 c = comp(e);
-        m = c < m ? c : m;
-    }
+    const u64 m = mcol == 0xFFFFFFFFu ? ~0ull : pack(mo, mcol);
     // the j first thread minima of this wave; its contribution is the j-th
     const u32 j = (k + RW_THREADS / WAVE - 1) / (RW_THREADS / WAVE);
     u64 mine = m, last = 0;
@@ -104,37 +208,36 @@ __global__ __launch_bounds__(RW_THREADS) void k_rows_fwd(const u32 *__restrict__
     }
     if (lane == 0) sh.wthr[w] = last;
     if (tid == 0) sh.ccount = 0u;
+    sh.hist[tid] = 0u;
     __syncthreads();
     u64 T = 0;
 #pragma unroll
     for (int i = 0; i < RW_THREADS / WAVE; ++i) T = sh.wthr[i] > T ? sh.wthr[i] : T;
 
     // candidates: every element at or before T
+    const u32 th = (u32)(T >> 32), tl = (u32)T;
+    const u32 tb1 = opaque(tid);
 #pragma unroll
     for (int e = 0; e < IPT; ++e) {
-        const u64 c = comp(e);
-        cand_append(sh, c <= T && c != ~0ull, c);
+        const u32 col = (u32)e * RW_THREADS + tb1;
+        const bool take = col < N && (o[e] < th || (o[e] == th && col <= tl));
+        cand_append(sh, take, o[e], col);
     }
     __syncthreads();
     u32 mc = sh.ccount;
     if (mc > RW_CAND) {
         // too many equal keys: the k-th element exactly, then the k first
-        u64 v[IPT];
-        int cnt = 0;                        // slots holding a column (a prefix)
-#pragma unroll
-        for (int e = 0; e < IPT; ++e) {
-            v[e] = comp(e);
-            cnt += (u32)e * RW_THREADS + tid < N ? 1 : 0;
-        }
-        const u64 ranks[2] = {(u64)k - 1, 0ull};
-        const bool act[2] = {true, false};
-        u64 tau2[2];
-        radix_select<IPT>(v, cnt, ranks, act, tau2, sh.rs);
-        __syncthreads();
+        const u64 tau = rw_select<IPT>(o, N, k - 1, sh);
+        const u32 uh = (u32)(tau >> 32), ul = (u32)tau;
         if (tid == 0) sh.ccount = 0u;
         __syncthreads();
+        const u32 tb2 = opaque(tid);
 #pragma unroll
-        for (int e = 0; e < IPT; ++e) cand_append(sh, e < cnt && v[e] <= tau2[0], v[e]);
+        for (int e = 0; e < IPT; ++e) {
+            const u32 col = (u32)e * RW_THREADS + tb2;
+            const bool take = col < N && (o[e] < uh || (o[e] == uh && col <= ul));
+            cand_append(sh, take, o[e], col);
+        }
         __syncthreads();
         mc = sh.ccount;
     }
