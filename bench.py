@@ -139,6 +139,29 @@ def bench_select(args):
     for k in ks:
         ctxs[k].kernel_times()
 
+    # the canonical output order (TOPK_SORTED), reported beside the step (not
+    # part of it): the same selections with their outputs sorted by (key,
+    # position), timed the same way; one workspace serves the three
+    sorted_order = {}
+    ws_sorted = torch.empty(max(ctxs[k].workspace_bytes(n, tk.TOPK_SORTED) for k in ks),
+                            dtype=torch.uint8, device=dev)
+    for k in ks:
+        ctxs[k].set_param("timing", 0)
+        r = ctxs[k].select(keys, k, workspace=ws_sorted, sorted=True)
+        torch.cuda.synchronize()
+        if int(r["idx"][-1].item()) != int(r["kth_idx"].item()):
+            raise SystemExit("sorted output of k=%d does not end with the k-th pair" % k)
+        reps = 3
+        ek[0].record(stream)
+        for _ in range(reps):
+            ctxs[k].select(keys, k, workspace=ws_sorted, sorted=True)
+        ek[1].record(stream)
+        torch.cuda.synchronize()
+        ms = ek[0].elapsed_time(ek[1]) / reps
+        sorted_order[str(k)] = {"ms": round(ms, 4), "sort_ms": round(ms - per_k_ms[k], 4)}
+    del ws_sorted
+    log("sorted order: %s" % sorted_order)
+
     ms_per_step = total_ms / args.steps
     value = len(ks) * n / (ms_per_step * 1e-3) / 1e9
 
@@ -225,6 +248,9 @@ def bench_select(args):
                    "parallelism": "none (1 GPU)"},
         "per_k": per_k, "tuned": tuned if (args.tuning_prefix or not args.no_tune) else None,
         "roofline": roof, "cpu_baseline": cpu,
+        "sorted_order": {"how": "the same selections with TOPK_SORTED (outputs in (key, position) "
+                                "order), mean of 3 calls; sort_ms = the sorted call minus the "
+                                "plain one", **sorted_order},
     }
 
 

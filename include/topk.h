@@ -53,6 +53,7 @@ extern "C" {
 
 /* Flags. */
 #define TOPK_LARGEST 1u          /* select the k largest instead of the k smallest  */
+#define TOPK_SORTED 2u           /* single selection: out_idx in (key, position) order */
 #define TOPK_WRITE_KEYS 4u       /* also write the selected keys (original bits)   */
 #define TOPK_TRACE 8u            /* record every round's sample in the workspace   */
 #define TOPK_GRAPH 16u           /* batched: launch through a cached hipGraph      */
@@ -116,9 +117,16 @@ size_t topk_workspace_bytes(const topk_ctx *ctx, uint64_t n, uint32_t flags);
  *   out_idx   [k]  positions of the selected keys, each exactly once, in an
  *                  unspecified order that may differ between calls (the
  *                  sweeps hand out output ranges in the order their
- *                  workgroups arrive); sort them for a canonical order
+ *                  workgroups arrive); with TOPK_SORTED in the unique order
+ *                  of Section 2: keys ascending (descending with
+ *                  TOPK_LARGEST), ties by ascending position, NaN last
+ *                  (first with TOPK_LARGEST), so out_idx[k-1] == kth_idx.
+ *                  The order costs a radix sort of the k (order word,
+ *                  position) pairs after the selection: about 16 k bytes of
+ *                  traffic per pass, one pass per 8-bit digit that differs
+ *                  among the pairs
  *   out_keys  [k]  NULL, or (with TOPK_WRITE_KEYS) keys[out_idx[i]], bits as in
- *                  the input
+ *                  the input (in out_idx's order, also with TOPK_SORTED)
  *   kth_key   [1]  the key of rank k (input bits, e.g. -0.0 and NaN payloads kept)
  *   kth_idx   [1]  its position; out_idx always contains it
  *   status    [1]  NULL or the device status word: TOPK_STATUS_OK, or

@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtopk.so")
 
 TOPK_LARGEST = 1
+TOPK_SORTED = 2
 TOPK_WRITE_KEYS = 4
 TOPK_TRACE = 8
 TOPK_GRAPH = 16
@@ -152,12 +153,14 @@ class Context:
         return torch.empty(max(self.workspace_bytes(n, flags), 256), dtype=torch.uint8,
                            device=self.device)
 
-    def select(self, keys, k, largest=False, write_keys=False, trace=False, workspace=None):
+    def select(self, keys, k, largest=False, write_keys=False, trace=False, workspace=None,
+               sorted=False):
         """Select the k smallest (or largest) of a 1-D u32/f32 CUDA tensor.
 
         u32 keys are passed as torch.uint32 or as torch.int32 holding the bits.
         Returns a dict of device tensors: ``idx`` (int32 holding u32 positions,
-        length k, in an unspecified order), ``kth_key`` (1 element, dtype of keys), ``kth_idx``,
+        length k, in an unspecified order, or with ``sorted`` in the order by
+        (key, position)), ``kth_key`` (1 element, dtype of keys), ``kth_idx``,
         ``status`` and, with ``write_keys``, ``keys``.  ``workspace`` is kept
         in the dict for trace queries.
         """
@@ -171,7 +174,7 @@ class Context:
             raise TypeError("keys must be float32 or uint32/int32 bits")
         n = keys.numel()
         flags = (TOPK_LARGEST if largest else 0) | (TOPK_WRITE_KEYS if write_keys else 0) | \
-                (TOPK_TRACE if trace else 0)
+                (TOPK_TRACE if trace else 0) | (TOPK_SORTED if sorted else 0)
         dev = keys.device
         out_idx = torch.empty(max(k, 1), dtype=torch.int32, device=dev)
         kth_key = torch.empty(1, dtype=keys.dtype, device=dev)

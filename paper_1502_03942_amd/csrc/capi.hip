@@ -17,6 +17,7 @@
 
 #include "../../include/topk.h"
 #include "select.hpp"
+#include "sort.hpp"
 #include "ctx.hpp"
 
 using namespace topk;
@@ -27,7 +28,7 @@ constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t x, size_t a = ALIGN) { return (x + a - 1) / a * a; }
 
 struct Layout {
-    size_t state, hs, seg, band[4], trace, total;
+    size_t state, hs, seg, band[4], trace, sort, total;
     uint32_t band_cap, band_alloc;
 };
 
@@ -52,6 +53,8 @@ Layout make_layout(const topk_ctx *c, uint64_t n, uint32_t flags)
     }
     L.trace = off;
     if (flags & TOPK_TRACE) off = align_up(off + (size_t)R_TRACE * TRACE_STRIDE * sizeof(uint32_t));
+    L.sort = off;
+    if (flags & TOPK_SORTED) off = align_up(off + sort_ws_bytes(n));
     L.total = off;
     return L;
 }
@@ -153,7 +156,7 @@ int select_common(topk_ctx *c, const K *keys, uint64_t n, uint64_t k, uint32_t f
 {
     if (!c || !keys || !out_idx || !kth_key || !kth_idx || !ws) return TOPK_E_INVALID;
     if (n == 0 || k == 0 || k > n || n > 0xFFFFFFFFull) return TOPK_E_INVALID;
-    if (flags & ~(TOPK_LARGEST | TOPK_WRITE_KEYS | TOPK_TRACE)) return TOPK_E_INVALID;
+    if (flags & ~(TOPK_LARGEST | TOPK_WRITE_KEYS | TOPK_TRACE | TOPK_SORTED)) return TOPK_E_INVALID;
     if ((flags & TOPK_WRITE_KEYS) && !out_keys) return TOPK_E_INVALID;
     if (((uintptr_t)keys & 3u) || ((uintptr_t)ws & (ALIGN - 1))) return TOPK_E_INVALID;
     const Layout L = make_layout(c, n, flags);
@@ -218,8 +221,11 @@ int select_common(topk_ctx *c, const K *keys, uint64_t n, uint64_t k, uint32_t f
         tm.cap = (int)c->ev_kind.size();
         tm.used = c->ev_used;
     }
-    const hipError_t e = launch_select(a, P, stream, c->timing > 0 ? &tm : nullptr);
+    hipError_t e = launch_select(a, P, stream, c->timing > 0 ? &tm : nullptr);
     if (c->timing > 0) c->ev_used = tm.used;
+    if (e == hipSuccess && (flags & TOPK_SORTED))
+        e = sort_selected((const uint32_t *)keys, n, is_f32, (flags & TOPK_LARGEST) != 0, out_idx,
+                          a.out_keys, k, w + L.sort, stream);
     return e == hipSuccess ? TOPK_OK : TOPK_E_HIP;
 }
 
