@@ -12,7 +12,7 @@
 //            sums, chunk scans), and a stable scatter
 //   out      positions (and keys) back to the caller's arrays
 // Every kernel is enqueued for every pass; a pass the plan skips returns at
-// once.  The scatter is stable: a tile is taken in rounds of SS_THREADS
+// once.  The scatter is stable: a tile is taken in rounds of SX_THREADS
 // pairs in order; within a round the pairs of one digit are ranked by wave
 // match masks (eight ballots) and the waves' counts of that digit, across
 // rounds by a running count per digit.
@@ -23,6 +23,8 @@
 
 namespace topk {
 
+typedef uint16_t u16;
+
 constexpr int SS_THREADS = 256;
 constexpr int SS_WAVES = SS_THREADS / WAVE;
 constexpr int SS_ROUNDS = 16;
@@ -30,6 +32,11 @@ constexpr u32 SS_TILE = SS_THREADS * SS_ROUNDS;     // pairs per tile and pass
 constexpr int SS_BITS = 8;
 constexpr u32 SS_BINS = 1u << SS_BITS;
 constexpr int SS_PASSES = 64 / SS_BITS;
+constexpr int SX_THREADS = 1024;                    // scatter: a round of 1024 pairs
+constexpr int SX_WAVES = SX_THREADS / WAVE;
+constexpr int SX_ROUNDS = SS_TILE / SX_THREADS;
+static_assert(SS_TILE % SX_THREADS == 0, "whole scatter rounds per tile");
+static_assert(SS_TILE <= 65536, "16-bit local prefixes");
 constexpr int SC_THREADS = 1024;
 constexpr u32 SC_CHUNK = SC_THREADS * 4;            // scan entries per chunk
 static_assert(SS_BINS == (u32)SS_THREADS, "one digit per thread");
@@ -37,6 +44,7 @@ static_assert(SS_BINS == (u32)SS_THREADS, "one digit per thread");
 struct SortWs {
     u64 *buf[2];        // ping-pong pairs
     u32 *hist;          // [SS_BINS][tiles], scanned in place
+    u32 *hcount;        // [SS_BINS][tiles], the same counts unscanned
     u32 *chunk;         // chunk sums of the scan
     u64 *bits;          // [0] OR, [1] AND of all pairs
     u32 *plan;          // [p]: source buffer of pass p, bit 31: the pass runs; [SS_PASSES]: result
@@ -57,6 +65,7 @@ SortWs carve(void *ws, u64 k)
     s.buf[0] = (u64 *)(w + off); off = salign(off + k * sizeof(u64));
     s.buf[1] = (u64 *)(w + off); off = salign(off + k * sizeof(u64));
     s.hist = (u32 *)(w + off);   off = salign(off + tiles_of(k) * SS_BINS * sizeof(u32));
+    s.hcount = (u32 *)(w + off); off = salign(off + tiles_of(k) * SS_BINS * sizeof(u32));
     s.chunk = (u32 *)(w + off);  off = salign(off + chunks_of(tiles_of(k) * SS_BINS) * sizeof(u32));
     s.bits = (u64 *)(w + off);   off = salign(off + 2 * sizeof(u64));
     s.plan = (u32 *)(w + off);
@@ -71,10 +80,25 @@ size_t sort_ws_bytes(uint64_t n)
     off = salign(off + n * sizeof(u64));
     off = salign(off + n * sizeof(u64));
     off = salign(off + tiles_of(n) * SS_BINS * sizeof(u32));
+    off = salign(off + tiles_of(n) * SS_BINS * sizeof(u32));
     off = salign(off + chunks_of(tiles_of(n) * SS_BINS) * sizeof(u32));
     off = salign(off + 2 * sizeof(u64));
     off = salign(off + (SS_PASSES + 1) * sizeof(u32));
     return off;
+}
+
+// Lanes of this wave holding a pair whose digit equals this lane's (valid
+// lanes only): eight ballots, one per digit bit.
+__device__ __forceinline__ u64 same_digit(bool valid, u32 d)
+{
+    u64 peer = ballot(valid);
+#pragma unroll
+    for (int b = 0; b < SS_BITS; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const u64 m = ballot(bit);
+        peer &= bit ? m : ~m;
+    }
+    return peer;
 }
 
 __global__ void k_ss_init(SortWs w)
@@ -144,13 +168,18 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_hist(SortWs w, u64 k, u32 til
     const u64 *__restrict__ src = w.buf[pl & 1u];
     const u64 base = (u64)blockIdx.x * SS_TILE;
     const int sh = SS_BITS * p;
-#pragma unroll 4
+    // one LDS atomic per group of same-digit lanes (a few digits, such as
+    // the exponent bits of real keys, would otherwise serialise the adds)
     for (int r = 0; r < SS_ROUNDS; ++r) {
         const u64 i = base + (u64)r * SS_THREADS + t;
-        if (i < k) atomicAdd(&h[(u32)(src[i] >> sh) & (SS_BINS - 1)], 1u);
+        const bool valid = i < k;
+        const u32 d = valid ? (u32)(src[i] >> sh) & (SS_BINS - 1) : 0u;
+        const u64 peer = same_digit(valid, d);
+        if (valid && mbcnt(peer) == 0) atomicAdd(&h[d], (u32)__popcll(peer));
     }
     __syncthreads();
     w.hist[(u64)t * tiles + blockIdx.x] = h[t];
+    w.hcount[(u64)t * tiles + blockIdx.x] = h[t];
 }
 
 // scan, step 1: the sum of each chunk of SC_CHUNK entries
@@ -210,59 +239,75 @@ __global__ __launch_bounds__(SC_THREADS) void k_ss_scan3(SortWs w, u64 entries, 
     }
 }
 
-// stable scatter of tile blockIdx.x by digit p
-__global__ __launch_bounds__(SS_THREADS) void k_ss_scatter(SortWs w, u64 k, u32 tiles, int p)
+// stable scatter of tile blockIdx.x by digit p.  The tile is first placed
+// in LDS in digit order (SX_ROUNDS rounds of SX_THREADS pairs in order; per
+// round the leader of each group of same-digit lanes stores the group's size
+// for its wave, one thread per digit turns the waves' sizes into exclusive
+// prefixes plus the digit's running count, and every pair goes to its local
+// slot), then written out in that order, so each digit's pairs leave as one
+// contiguous run.  The per-wave sizes alternate between two buffers by round
+// parity: a round's buffer is cleared during the next round, after every
+// reader has passed its first barrier, and written again two rounds later.
+__global__ __launch_bounds__(SX_THREADS) void k_ss_scatter(SortWs w, u64 k, u32 tiles, int p)
 {
     const u32 pl = w.plan[p];
     if (!(pl >> 31)) return;
-    __shared__ u32 off[SS_BINS];             // first output slot of each digit in this tile
-    __shared__ u32 run[SS_BINS];             // pairs of each digit placed by earlier rounds
-    __shared__ u32 wc[2][SS_WAVES][SS_BINS]; // this round's count per wave and digit (by parity)
-    const u32 t = threadIdx.x, lane = lane_id();
+    __shared__ u64 stage[SS_TILE];               // the tile in digit order
+    __shared__ u32 off[SS_BINS];                 // first output slot of each digit in this tile
+    __shared__ u32 loff[SS_BINS];                // first local slot of each digit
+    __shared__ u32 run[SS_BINS];                 // pairs of each digit placed by earlier rounds
+    __shared__ u16 wc[2][SX_WAVES][SS_BINS];     // per wave and digit: size, then exclusive prefix
+    __shared__ u32 scan[SX_THREADS / WAVE];
+    const u32 t = threadIdx.x;
     const u32 wv = t / WAVE;
-    off[t] = w.hist[(u64)t * tiles + blockIdx.x];
-    run[t] = 0u;
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int v = 0; v < SS_WAVES; ++v) wc[q][v][t] = 0u;
+    const u32 cnt_t = t < SS_BINS ? w.hcount[(u64)t * tiles + blockIdx.x] : 0u;
+    if (t < SS_BINS) {
+        off[t] = w.hist[(u64)t * tiles + blockIdx.x];
+        run[t] = 0u;
+    }
+    for (u32 j = t; j < 2u * SX_WAVES * SS_BINS; j += SX_THREADS) (&wc[0][0][0])[j] = 0;
+    u32 tot;
+    const u32 lo = block_excl_scan<SX_THREADS>(cnt_t, scan, &tot);
+    if (t < SS_BINS) loff[t] = lo;
     __syncthreads();
     const u64 *__restrict__ src = w.buf[pl & 1u];
     u64 *__restrict__ dst = w.buf[(pl & 1u) ^ 1u];
     const u64 base = (u64)blockIdx.x * SS_TILE;
     const int sh = SS_BITS * p;
-    for (int r = 0; r < SS_ROUNDS; ++r) {
+    for (int r = 0; r < SX_ROUNDS; ++r) {
         const u32 par = (u32)r & 1u;
-        const u64 i = base + (u64)r * SS_THREADS + t;
+        const u64 i = base + (u64)r * SX_THREADS + t;
         const bool valid = i < k;
         const u64 x = valid ? src[i] : 0ull;
         const u32 d = (u32)(x >> sh) & (SS_BINS - 1);
-        // lanes of this wave with the same digit (valid lanes only)
-        u64 peer = ballot(valid);
-#pragma unroll
-        for (int b = 0; b < SS_BITS; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const u64 m = ballot(bit);
-            peer &= bit ? m : ~m;
-        }
+        const u64 peer = same_digit(valid, d);
         const u32 before = mbcnt(peer);          // same-digit lanes below this one
-        if (valid && before == 0) wc[par][wv][d] = (u32)__popcll(peer);
+        if (valid && before == 0) wc[par][wv][d] = (u16)__popcll(peer);
+        __syncthreads();
+        if (t < SS_BINS) {
+            u32 acc = run[t];
+#pragma unroll
+            for (int v = 0; v < SX_WAVES; ++v) {
+                const u32 c = wc[par][v][t];
+                wc[par][v][t] = (u16)acc;        // at most SS_TILE - 1
+                acc += c;
+                wc[par ^ 1u][v][t] = 0;          // the previous round's, read before this round's barrier
+            }
+            run[t] = acc;
+        }
         __syncthreads();
         if (valid) {
-            u32 pos = off[d] + run[d] + before;
-            for (u32 v = 0; v < wv; ++v) pos += wc[par][v][d];
-            if (pos < k) dst[pos] = x;
+            const u32 lpos = loff[d] + wc[par][wv][d] + before;
+            if (lpos < SS_TILE) stage[lpos] = x;
         }
-        __syncthreads();
-        // digit t: account this round's pairs, clear this parity's counts
-        // (rewritten two rounds later, after the next round's barriers)
-        u32 add = 0;
-#pragma unroll
-        for (int v = 0; v < SS_WAVES; ++v) {
-            add += wc[par][v][t];
-            wc[par][v][t] = 0u;
-        }
-        run[t] += add;
+    }
+    __syncthreads();
+    const u32 nt = k - base < SS_TILE ? (u32)(k - base) : SS_TILE;
+    for (u32 j = t; j < nt; j += SX_THREADS) {
+        const u64 x = stage[j];
+        const u32 d = (u32)(x >> sh) & (SS_BINS - 1);
+        const u64 g = (u64)off[d] + (j - loff[d]);
+        if (g < k) dst[g] = x;
     }
 }
 
@@ -303,7 +348,7 @@ hipError_t sort_selected(const uint32_t *keys, uint64_t n, bool is_f32, bool lar
         hipLaunchKernelGGL(k_ss_scan1, dim3((unsigned)nch), dim3(SC_THREADS), 0, stream, w, entries, p);
         hipLaunchKernelGGL(k_ss_scan2, dim3(1), dim3(SC_THREADS), 0, stream, w, (u32)nch, p);
         hipLaunchKernelGGL(k_ss_scan3, dim3((unsigned)nch), dim3(SC_THREADS), 0, stream, w, entries, p);
-        hipLaunchKernelGGL(k_ss_scatter, dim3((unsigned)tiles), dim3(SS_THREADS), 0, stream, w, k, (u32)tiles, p);
+        hipLaunchKernelGGL(k_ss_scatter, dim3((unsigned)tiles), dim3(SX_THREADS), 0, stream, w, k, (u32)tiles, p);
     }
     hipLaunchKernelGGL(k_ss_out, gstream, dim3(SS_THREADS), 0, stream, keys, n, out_idx, out_keys, k, w);
     return hipGetLastError();
