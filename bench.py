@@ -143,9 +143,9 @@ def bench_select(args):
     # part of it): the same selections with their outputs sorted by (key,
     # position), timed the same way; one workspace serves the three
     sorted_order = {}
-    ws_sorted = torch.empty(max(ctxs[k].workspace_bytes(n, tk.TOPK_SORTED) for k in ks),
-                            dtype=torch.uint8, device=dev)
-    for k in ks:
+    ws_sorted = torch.empty(max(ctxs[k].workspace_bytes(n, tk.TOPK_SORTED) for k in ks)
+                            if not args.no_sorted else 256, dtype=torch.uint8, device=dev)
+    for k in (ks if not args.no_sorted else ()):
         ctxs[k].set_param("timing", 0)
         r = ctxs[k].select(keys, k, workspace=ws_sorted, sorted=True)
         torch.cuda.synchronize()
@@ -611,6 +611,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-sorted", action="store_true",
+                    help="skip the timing of the sorted output order (TOPK_SORTED)")
     ap.add_argument("--no-tune", action="store_true",
                     help="batched form with the default parameters (no autotuner run)")
     ap.add_argument("--tuning-prefix", metavar="PREFIX",
