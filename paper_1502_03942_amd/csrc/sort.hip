@@ -161,25 +161,26 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_hist(SortWs w, u64 k, u32 til
 {
     const u32 pl = w.plan[p];
     if (!(pl >> 31)) return;
-    __shared__ u32 h[SS_BINS];
+    __shared__ u32 hw[SS_WAVES][SS_BINS];     // one histogram per wave
     const u32 t = threadIdx.x;
-    h[t] = 0u;
+#pragma unroll
+    for (int v = 0; v < SS_WAVES; ++v) hw[v][t] = 0u;
     __syncthreads();
     const u64 *__restrict__ src = w.buf[pl & 1u];
     const u64 base = (u64)blockIdx.x * SS_TILE;
     const int sh = SS_BITS * p;
-    // one LDS atomic per group of same-digit lanes (a few digits, such as
-    // the exponent bits of real keys, would otherwise serialise the adds)
+    const u32 wv = t / WAVE;
+#pragma unroll 4
     for (int r = 0; r < SS_ROUNDS; ++r) {
         const u64 i = base + (u64)r * SS_THREADS + t;
-        const bool valid = i < k;
-        const u32 d = valid ? (u32)(src[i] >> sh) & (SS_BINS - 1) : 0u;
-        const u64 peer = same_digit(valid, d);
-        if (valid && mbcnt(peer) == 0) atomicAdd(&h[d], (u32)__popcll(peer));
+        if (i < k) atomicAdd(&hw[wv][(u32)(src[i] >> sh) & (SS_BINS - 1)], 1u);
     }
     __syncthreads();
-    w.hist[(u64)t * tiles + blockIdx.x] = h[t];
-    w.hcount[(u64)t * tiles + blockIdx.x] = h[t];
+    u32 c = 0;
+#pragma unroll
+    for (int v = 0; v < SS_WAVES; ++v) c += hw[v][t];
+    w.hist[(u64)t * tiles + blockIdx.x] = c;
+    w.hcount[(u64)t * tiles + blockIdx.x] = c;
 }
 
 // scan, step 1: the sum of each chunk of SC_CHUNK entries
