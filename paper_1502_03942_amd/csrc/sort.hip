@@ -170,11 +170,16 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_hist(SortWs w, u64 k, u32 til
     const u64 base = (u64)blockIdx.x * SS_TILE;
     const int sh = SS_BITS * p;
     const u32 wv = t / WAVE;
-#pragma unroll 4
+    // every load of the tile is issued before the first add
+    u64 xr[SS_ROUNDS];
+#pragma unroll
     for (int r = 0; r < SS_ROUNDS; ++r) {
         const u64 i = base + (u64)r * SS_THREADS + t;
-        if (i < k) atomicAdd(&hw[wv][(u32)(src[i] >> sh) & (SS_BINS - 1)], 1u);
+        xr[r] = i < k ? src[i] : 0ull;
     }
+#pragma unroll
+    for (int r = 0; r < SS_ROUNDS; ++r)
+        if (base + (u64)r * SS_THREADS + t < k) atomicAdd(&hw[wv][(u32)(xr[r] >> sh) & (SS_BINS - 1)], 1u);
     __syncthreads();
     u32 c = 0;
 #pragma unroll
@@ -275,11 +280,19 @@ __global__ __launch_bounds__(SX_THREADS) void k_ss_scatter(SortWs w, u64 k, u32 
     u64 *__restrict__ dst = w.buf[(pl & 1u) ^ 1u];
     const u64 base = (u64)blockIdx.x * SS_TILE;
     const int sh = SS_BITS * p;
+    // the thread's pairs of every round, loaded together
+    u64 xr[SX_ROUNDS];
+#pragma unroll
+    for (int r = 0; r < SX_ROUNDS; ++r) {
+        const u64 i = base + (u64)r * SX_THREADS + t;
+        xr[r] = i < k ? src[i] : 0ull;
+    }
+#pragma unroll
     for (int r = 0; r < SX_ROUNDS; ++r) {
         const u32 par = (u32)r & 1u;
         const u64 i = base + (u64)r * SX_THREADS + t;
         const bool valid = i < k;
-        const u64 x = valid ? src[i] : 0ull;
+        const u64 x = xr[r];
         const u32 d = (u32)(x >> sh) & (SS_BINS - 1);
         const u64 peer = same_digit(valid, d);
         const u32 before = mbcnt(peer);          // same-digit lanes below this one
