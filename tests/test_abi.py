@@ -42,3 +42,15 @@ def test_strerror_without_device():
     lib.topk_strerror.restype = ctypes.c_char_p
     assert lib.topk_strerror(0) == b"ok"
     assert lib.topk_strerror(-2) == b"workspace too small"
+
+
+def test_binding_flags_match_header():
+    # every TOPK_* flag the binding passes has the value the header defines
+    import paper_1502_03942_amd as tk
+    text = open(HEADER).read()
+    defines = {m.group(1): int(m.group(2)) for m in
+               re.finditer(r"^#define\s+(TOPK_[A-Z_]+)\s+(\d+)u?\b", text, flags=re.M)}
+    names = [n for n in dir(tk) if n.startswith("TOPK_") and isinstance(getattr(tk, n), int)]
+    assert {"TOPK_LARGEST", "TOPK_SORTED", "TOPK_WRITE_KEYS", "TOPK_TRACE", "TOPK_GRAPH"} <= set(names)
+    for n in names:
+        assert n in defines and getattr(tk, n) == defines[n], n
