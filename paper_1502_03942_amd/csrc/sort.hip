@@ -2,10 +2,11 @@
 // the k selected positions are rewritten in the unique order by (key,
 // position) of §2.  A least-significant-digit radix sort of the 64-bit pairs
 // (order word << 32 | position), 8-bit digits:
-//   compose  gather each selected key, form its pair; OR and AND of all pairs
-//   plan     a digit that is the same in every pair needs no pass (the pass
-//            would be the identity); the plan records each pass's source
-//            buffer and whether it runs
+//   compose  gather each selected key, form its pair; each workgroup's OR
+//            and AND of its pairs (no atomics: every workgroup its own slot)
+//   plan     reduce the slots; a digit that is the same in every pair needs
+//            no pass (the pass would be the identity); the plan records each
+//            pass's source buffer and whether it runs
 //   per pass histogram of the digit per tile of SS_TILE pairs (bin-major, so
 //            one flat exclusive scan gives every (digit, tile) its first
 //            output slot), the scan (chunk sums, one-workgroup scan of the
@@ -37,6 +38,8 @@ constexpr int SX_WAVES = SX_THREADS / WAVE;
 constexpr int SX_ROUNDS = SS_TILE / SX_THREADS;
 static_assert(SS_TILE % SX_THREADS == 0, "whole scatter rounds per tile");
 static_assert(SS_TILE <= 65536, "16-bit local prefixes");
+constexpr u32 SP_BLOCKS = 2048;                     // compose workgroups at most
+constexpr int SP_THREADS = 1024;                    // plan: one workgroup reduces the slots
 constexpr int SC_THREADS = 1024;
 constexpr u32 SC_CHUNK = SC_THREADS * 4;            // scan entries per chunk
 static_assert(SS_BINS == (u32)SS_THREADS, "one digit per thread");
@@ -46,7 +49,7 @@ struct SortWs {
     u32 *hist;          // [SS_BINS][tiles], scanned in place
     u32 *hcount;        // [SS_BINS][tiles], the same counts unscanned
     u32 *chunk;         // chunk sums of the scan
-    u64 *bits;          // [0] OR, [1] AND of all pairs
+    u64 *bits;          // [2 b], [2 b + 1]: OR and AND of compose workgroup b's pairs
     u32 *plan;          // [p]: source buffer of pass p, bit 31: the pass runs; [SS_PASSES]: result
 };
 
@@ -67,7 +70,7 @@ SortWs carve(void *ws, u64 k)
     s.hist = (u32 *)(w + off);   off = salign(off + tiles_of(k) * SS_BINS * sizeof(u32));
     s.hcount = (u32 *)(w + off); off = salign(off + tiles_of(k) * SS_BINS * sizeof(u32));
     s.chunk = (u32 *)(w + off);  off = salign(off + chunks_of(tiles_of(k) * SS_BINS) * sizeof(u32));
-    s.bits = (u64 *)(w + off);   off = salign(off + 2 * sizeof(u64));
+    s.bits = (u64 *)(w + off);   off = salign(off + 2 * SP_BLOCKS * sizeof(u64));
     s.plan = (u32 *)(w + off);
     return s;
 }
@@ -82,7 +85,7 @@ size_t sort_ws_bytes(uint64_t n)
     off = salign(off + tiles_of(n) * SS_BINS * sizeof(u32));
     off = salign(off + tiles_of(n) * SS_BINS * sizeof(u32));
     off = salign(off + chunks_of(tiles_of(n) * SS_BINS) * sizeof(u32));
-    off = salign(off + 2 * sizeof(u64));
+    off = salign(off + 2 * SP_BLOCKS * sizeof(u64));
     off = salign(off + (SS_PASSES + 1) * sizeof(u32));
     return off;
 }
@@ -99,14 +102,6 @@ __device__ __forceinline__ u64 same_digit(bool valid, u32 d)
         peer &= bit ? m : ~m;
     }
     return peer;
-}
-
-__global__ void k_ss_init(SortWs w)
-{
-    if (threadIdx.x == 0) {
-        w.bits[0] = 0ull;
-        w.bits[1] = ~0ull;
-    }
 }
 
 template <bool IS_F32, bool LARGEST>
@@ -138,15 +133,34 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_compose(const u32 *__restrict
             vo |= red[0][v];
             va &= red[1][v];
         }
-        atomicOr((unsigned long long *)&w.bits[0], (unsigned long long)vo);
-        atomicAnd((unsigned long long *)&w.bits[1], (unsigned long long)va);
+        w.bits[2 * blockIdx.x] = vo;
+        w.bits[2 * blockIdx.x + 1] = va;
     }
 }
 
-__global__ void k_ss_plan(SortWs w)
+__global__ __launch_bounds__(SP_THREADS) void k_ss_plan(SortWs w, u32 nblocks)
 {
+    __shared__ u64 red[2][SP_THREADS / WAVE];
+    u64 vo = 0ull, va = ~0ull;
+    for (u32 b = threadIdx.x; b < nblocks; b += SP_THREADS) {
+        vo |= w.bits[2 * b];
+        va &= w.bits[2 * b + 1];
+    }
+    for (int d = 1; d < WAVE; d <<= 1) {
+        vo |= __shfl_xor(vo, d, WAVE);
+        va &= __shfl_xor(va, d, WAVE);
+    }
+    if (lane_id() == 0) {
+        red[0][threadIdx.x / WAVE] = vo;
+        red[1][threadIdx.x / WAVE] = va;
+    }
+    __syncthreads();
     if (threadIdx.x != 0) return;
-    const u64 varies = w.bits[0] ^ w.bits[1];
+    for (int v = 1; v < SP_THREADS / WAVE; ++v) {
+        vo |= red[0][v];
+        va &= red[1][v];
+    }
+    const u64 varies = vo ^ va;
     u32 src = 0;
     for (int p = 0; p < SS_PASSES; ++p) {
         const bool run = ((varies >> (SS_BITS * p)) & (SS_BINS - 1)) != 0;
@@ -347,8 +361,8 @@ hipError_t sort_selected(const uint32_t *keys, uint64_t n, bool is_f32, bool lar
     const u64 nch = chunks_of(entries);
     if (tiles > 0x7FFFFFFFull || nch > 0x7FFFFFFFull) return hipErrorInvalidValue;
     const u64 gs = (k + SS_THREADS - 1) / SS_THREADS;
-    const dim3 gstream((unsigned)(gs < 8192 ? gs : 8192));
-    hipLaunchKernelGGL(k_ss_init, dim3(1), dim3(64), 0, stream, w);
+    const u32 ncomp = (u32)(gs < SP_BLOCKS ? gs : SP_BLOCKS);
+    const dim3 gstream(ncomp);
     if (is_f32) {
         if (largest) hipLaunchKernelGGL((k_ss_compose<true, true>), gstream, dim3(SS_THREADS), 0, stream, keys, out_idx, k, w);
         else hipLaunchKernelGGL((k_ss_compose<true, false>), gstream, dim3(SS_THREADS), 0, stream, keys, out_idx, k, w);
@@ -356,7 +370,7 @@ hipError_t sort_selected(const uint32_t *keys, uint64_t n, bool is_f32, bool lar
         if (largest) hipLaunchKernelGGL((k_ss_compose<false, true>), gstream, dim3(SS_THREADS), 0, stream, keys, out_idx, k, w);
         else hipLaunchKernelGGL((k_ss_compose<false, false>), gstream, dim3(SS_THREADS), 0, stream, keys, out_idx, k, w);
     }
-    hipLaunchKernelGGL(k_ss_plan, dim3(1), dim3(64), 0, stream, w);
+    hipLaunchKernelGGL(k_ss_plan, dim3(1), dim3(SP_THREADS), 0, stream, w, ncomp);
     for (int p = 0; p < SS_PASSES; ++p) {
         hipLaunchKernelGGL(k_ss_hist, dim3((unsigned)tiles), dim3(SS_THREADS), 0, stream, w, k, (u32)tiles, p);
         hipLaunchKernelGGL(k_ss_scan1, dim3((unsigned)nch), dim3(SC_THREADS), 0, stream, w, entries, p);
