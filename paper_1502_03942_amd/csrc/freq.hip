@@ -687,14 +687,13 @@ __global__ __launch_bounds__(FQ_THREADS) void k_fa_count(FqArgs a)
     __shared__ unsigned long long lds[SUM ? FA_W : FA_W / 2];
     u32 *cnt = reinterpret_cast<u32 *>(lds);
     unsigned long long *sums = lds;
-    const u32 nu = *a.nunits, sh = a.nb_log;
+    const u32 nu = *a.nunits;
     for (u32 u = blockIdx.x; u < nu; u += gridDim.x) {
         const u32 p = a.unit_part[u];
         const u32 tot = a.ptot[p];
         const u32 c0 = (u - a.ubase[p]) * FA_UNIT;
         const u32 s0 = a.pstart[p] + c0;
         const u32 s1 = a.pstart[p] + (tot - c0 < FA_UNIT ? tot : c0 + FA_UNIT);
-        const bool single = tot <= FA_UNIT;
         for (u32 i = threadIdx.x; i < FA_W; i += FQ_THREADS) {
             if (SUM) sums[i] = 0ull;
             else cnt[i] = 0u;
